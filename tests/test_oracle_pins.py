@@ -1,0 +1,321 @@
+"""Pins of the FP64 CPU oracle against things other than itself.
+
+Each test names what it checks the oracle against: an independent black-box
+implementation (rocRAND's Philox), exact integer identities, a finite
+difference, closed-form limits, deterministic integral-equation solutions of
+the same transport problem (tests/refsol.py), exact invariants of the method,
+and chi-square agreement of sampled states with the normalised gain
+distribution of Eq. (2).
+"""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import dmc_inputs as di
+import oracle
+import refsol
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+THREADS = min(8, os.cpu_count() or 1)
+
+
+# ---------------------------------------------------------------- Philox ----
+
+@pytest.fixture(scope="module")
+def rocrand_ref(tmp_path_factory):
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
+        pytest.skip("rocRAND headers / hipcc not available")
+    exe = str(tmp_path_factory.mktemp("rr") / "rocrand_philox_ref")
+    subprocess.check_call([hipcc, "-O1", "-o", exe, os.path.join(HERE, "rocrand_philox_ref.cpp")])
+    return exe
+
+
+def test_philox_matches_rocrand_black_box(rocrand_ref):
+    """Raw Philox4x32-10 blocks equal rocRAND's engine positioned at the same counter/key."""
+    rng = np.random.Generator(np.random.PCG64(123))
+    n = 20000
+    ctr = rng.integers(0, 2 ** 32, size=(n, 4), dtype=np.uint64)
+    ctr[:, 1] &= (1 << 29) - 1  # rocRAND's offset argument counts 32-bit words
+    key = rng.integers(0, 2 ** 32, size=(n, 2), dtype=np.uint64)
+    edges = [([0, 0, 0, 0], [0, 0]), ([2 ** 32 - 1, 0, 2 ** 32 - 1, 2 ** 32 - 1], [2 ** 32 - 1, 2 ** 32 - 1]),
+             ([1, 0, 0, 0], [0, 0]), ([0, 0, 0, 1], [0, 0]), ([0, 0, 1, 0], [1, 0])]
+    ctr = np.vstack([ctr, np.array([e[0] for e in edges], np.uint64)])
+    key = np.vstack([key, np.array([e[1] for e in edges], np.uint64)])
+    lines = "\n".join(" ".join(str(int(v)) for v in list(c) + list(k)) for c, k in zip(ctr, key))
+    out = subprocess.run([rocrand_ref], input=lines, capture_output=True, text=True, check=True).stdout
+    ref = np.array([[int(x) for x in ln.split()] for ln in out.strip().splitlines()], dtype=np.uint64)
+    got = np.array([oracle.philox(c, k) for c, k in zip(ctr, key)], dtype=np.uint64)
+    assert got.shape == ref.shape
+    assert np.array_equal(got, ref)
+
+
+def test_rng_block_counter_layout():
+    """(seed, pid, k, tag) map onto key = seed words and counter = (pid lo, pid hi, k, tag)."""
+    seed, pid, k, tag = 0x0123456789ABCDEF, 0x00000002FFFFFFFE, 77, 2
+    a = oracle.rng_block(seed, pid, k, tag)
+    b = oracle.philox([pid & 0xFFFFFFFF, pid >> 32, k, tag], [seed & 0xFFFFFFFF, seed >> 32])
+    assert np.array_equal(a, b)
+
+
+def test_uniform_words_statistics():
+    """Philox words behave as independent uniforms (KS on the open-interval map)."""
+    w = np.array([oracle.rng_block(9, pid, 0, 0) for pid in range(5000)], dtype=np.float64)
+    u = (w + 0.5) / 2.0 ** 32
+    for col in range(4):
+        assert stats.kstest(u[:, col], "uniform").pvalue > 1e-3
+
+
+# ---------------------------------------------------------- Tabulation ----
+
+HBAR, KB = 1.054571817e-34, 1.380649e-23
+
+
+def _bose_energy(omega, T):
+    return HBAR * omega / np.expm1(HBAR * omega / (KB * T))
+
+
+def test_dedT_matches_finite_difference():
+    """de^eq/dT equals a central difference of the Bose-Einstein mode energy."""
+    om = np.array([1e11, 3e12, 1e13, 5e13, 7.6e13])
+    for T in (4.0, 77.0, 300.0, 1000.0):
+        mat = di.Material([di.Branch(om, np.ones(5), np.ones(5), np.full(5, 5e3), np.full(5, 1e-11), 1.0)], T_eq=T)
+        dedT, Cm, sums = oracle.tabulate(mat)
+        h = T * 1e-5
+        fd = (_bose_energy(om, T + h) - _bose_energy(om, T - h)) / (2 * h)
+        ok = fd > 1e-300
+        assert np.allclose(dedT[ok], fd[ok], rtol=1e-7)
+        assert np.array_equal(Cm, dedT)  # D = domega = g = 1
+
+
+def test_heat_capacity_classical_limit():
+    """At T >> hbar omega / k_B every mode holds k_B: C_m -> k_B D domega g (error ~ x^2/12)."""
+    mat = di.silicon_like(n_bins=200, T_eq=1e6)
+    om, dom, dos, vg, tau, deg = mat.flat()
+    dedT, Cm, sums = oracle.tabulate(mat)
+    classical = KB * dos * dom * deg
+    x = HBAR * om / (KB * 1e6)
+    assert np.all(np.abs(Cm / classical - 1.0) <= x ** 2 / 12.0 + 1e-12)
+    assert sums[0] == pytest.approx(classical.sum(), rel=1e-4)
+    assert sums[1] == pytest.approx(np.sum(Cm / tau), rel=1e-12)
+    assert sums[2] == pytest.approx(np.sum(Cm * vg), rel=1e-12)
+
+
+# --------------------------------------------------------------- Alias ----
+
+def _implied_mass(t):
+    b = t["bits"]
+    U = 1 << (32 - b)
+    th = t["thresh"].astype(np.int64)
+    al = t["alias"].astype(np.int64)
+    mass = th.copy()
+    np.add.at(mass, al, U - th)
+    return mass
+
+
+@pytest.mark.parametrize("case", ["gray", "si_gain", "si_flux", "si_init", "random_zeros", "pow2", "two"])
+def test_alias_integer_identity(case):
+    """thresh_j + sum_{alias_i = j}(U - thresh_i) = q_j exactly; q sums to 2^32 and is within 1 of w/W 2^32."""
+    mat = di.silicon_like()
+    om, dom, dos, vg, tau, deg = mat.flat()
+    _, Cm, _ = oracle.tabulate(mat)
+    rng = np.random.Generator(np.random.PCG64(5))
+    w = {"gray": np.array([3.0]), "si_gain": Cm / tau, "si_flux": Cm * vg, "si_init": Cm,
+         "random_zeros": rng.exponential(size=1500) * (rng.random(1500) > 0.3),
+         "pow2": rng.random(1024), "two": np.array([1.0, 1.0])}[case]
+    t = oracle.alias(w)
+    q = t["q"].astype(np.int64)
+    assert int(q.sum()) == 2 ** 32
+    assert np.array_equal(_implied_mass(t), q)
+    assert np.all(t["thresh"] <= (1 << (32 - t["bits"])))
+    exact = np.zeros(q.shape[0])
+    exact[: w.shape[0]] = w / w.sum() * 2.0 ** 32
+    assert np.all(np.abs(q - exact) < 1.0 + 1e-6)
+    assert np.all(q[w.shape[0]:] == 0)
+
+
+def test_post_scatter_states_chi_square():
+    """Sampled post-scattering (omega, p) states follow the normalised D de/dT / tau (Eq. (2))."""
+    mat = di.silicon_like()
+    job = di.slab_job(mat, 1e-6, 12000, seed=31, n_bins=0)
+    hist = np.zeros(mat.n_states, np.uint64)
+    oracle.run_raw(job, threads=THREADS, hist=hist)
+    _, Cm, sums = oracle.tabulate(mat)
+    p = (Cm / mat.flat()[4]) / sums[1]
+    n = float(hist.sum())
+    assert n > 1e6
+    exp = n * p
+    # merge states in index order into groups with expected count >= 20
+    obs_g, exp_g = [], []
+    acc_o = acc_e = 0.0
+    for o, e in zip(hist.astype(np.float64), exp):
+        acc_o += o
+        acc_e += e
+        if acc_e >= 20.0:
+            obs_g.append(acc_o)
+            exp_g.append(acc_e)
+            acc_o = acc_e = 0.0
+    obs_g[-1] += acc_o
+    exp_g[-1] += acc_e
+    obs_g, exp_g = np.array(obs_g), np.array(exp_g)
+    chi2 = float(np.sum((obs_g - exp_g) ** 2 / exp_g))
+    pval = stats.chi2.sf(chi2, len(obs_g) - 1)
+    assert pval > 1e-3, (chi2, len(obs_g))
+
+
+# ------------------------------------------------------- Gray slab (C1) ----
+
+@pytest.fixture(scope="module")
+def gray_ref():
+    return refsol.gray_slab_richardson(100e-9 / (6000.0 * 16.7e-12), n_bins=20, M=600)
+
+
+def test_gray_slab_matches_integral_equation(gray_ref):
+    """C1 gray slab (s_L = 0.998): bin temperatures and transmission within 4 standard errors
+    of the exponential-integral solution of the same linearized gray problem."""
+    job = di.gray_slab(n=100_000)
+    res, raw, cnt, _ = oracle.simulate(job, threads=THREADS)
+    prep = oracle.prepare(job)
+    ref_T, ref_psi = gray_ref
+    Tn = res["T"] / 1.0  # walls at +-0.5 K: T / (T_h - T_c)
+    se = res["T_se"]
+    assert np.all(np.abs(Tn - ref_T) <= 4 * se), (Tn, ref_T, se)
+    assert np.all(se < 0.01)
+    unit = prep.C_tot * 6000.0 / 4.0
+    psi = res["q"] / unit
+    psi_se = res["q_se"] / unit
+    assert abs(psi.mean() - ref_psi) <= 4 * psi_se.mean()
+    # gray medium: the pseudo-temperature equals the energy temperature
+    assert np.allclose(res["Tloc"], res["T"], rtol=1e-12, atol=1e-15)
+
+
+def test_gray_slab_ballistic_limit():
+    """Without scattering every particle crosses: transmission Psi = 1 exactly, no scattering events."""
+    job = di.gray_slab(n=20_000, tau=1e3)
+    res, raw, cnt, _ = oracle.simulate(job, threads=THREADS)
+    prep = oracle.prepare(job)
+    psi = res["q"] / (prep.C_tot * 6000.0 / 4.0)
+    assert np.allclose(psi, 1.0, rtol=1e-12)
+    assert cnt["scatters"] == 0
+
+
+def test_gray_slab_diffusive_limit():
+    """s_L = 10: transmission matches the integral-equation value (itself matched to the Milne
+    diffusion form (4/3)/(s_L + 2 z0), z0 = 0.7104, in test_refsol_limits)."""
+    tau = 16.7e-12
+    L = 10 * 6000.0 * tau
+    job = di.gray_slab(n=100_000, L=L)
+    res, raw, cnt, _ = oracle.simulate(job, threads=THREADS)
+    prep = oracle.prepare(job)
+    unit = prep.C_tot * 6000.0 / 4.0
+    _, ref_psi = refsol.gray_slab(10.0, M=800)
+    psi = res["q"].mean() / unit
+    assert abs(psi - ref_psi) <= 4 * res["q_se"].mean() / unit
+
+
+def test_refsol_limits():
+    """The reference solver itself: Milne diffusion limit and the ballistic limit."""
+    _, p10 = refsol.gray_slab(10.0, M=800)
+    assert p10 == pytest.approx(refsol.milne_psi(10.0), rel=2e-4)
+    _, p0 = refsol.gray_slab(1e-6, M=50)
+    assert p0 == pytest.approx(1.0, abs=1e-5)
+
+
+# ------------------------------------------------------ Exact invariants ----
+
+@pytest.mark.parametrize("mat_name,L", [("gray", 100e-9), ("si", 100e-9), ("si", 1e-6)])
+def test_mean_scattering_events_invariant(mat_name, L):
+    """Steady slab with absorbing walls: mean scattering events per particle = 2 L G_tau / G_v,
+    and every bin sees the same net displacement (each particle starts and ends on a wall)."""
+    mat = di.gray_material() if mat_name == "gray" else di.silicon_like()
+    n = 40_000 if L < 5e-7 else 8_000
+    job = di.slab_job(mat, L, n, seed=11, n_bins=20)
+    res, raw, cnt, nscat = oracle.simulate(job, threads=THREADS, want_nscat=True)
+    _, _, sums = oracle.tabulate(mat)
+    expect = 2.0 * L * sums[1] / sums[2]
+    mean = nscat.mean()
+    se = nscat.std(ddof=1) / math.sqrt(n)
+    assert abs(mean - expect) <= 4.0 * se, (mean, expect, se)
+    q = res["q"]
+    assert np.allclose(q, q[0], rtol=1e-9)
+    assert cnt["absorbed"] == n and cnt["capped"] == 0
+
+
+def test_transient_energy_conservation_and_event_rate():
+    """Heated spot: at every snapshot time the grid plus overflow holds sum_i s_i exactly
+    (particles are conserved), and the mean number of scattering events by t_final is
+    t_final G_tau / C_tot (the initial state distribution ~ C is stationary)."""
+    mat = di.silicon_like()
+    job = di.heated_spot(n=6000, seed=3, material=mat, grid=8, n_times=6)
+    job.tally.times = tuple(np.array(job.tally.times) * 1e-2)  # up to 100 ps
+    res, raw, cnt, nscat = oracle.simulate(job, threads=THREADS, want_nscat=True)
+    parts = oracle.split_raw(oracle.prepare(job), raw)
+    total = parts["snap"].sum(axis=1)
+    assert np.all(total == job.n_particles)  # every particle is positive (dT > 0) and alive
+    _, _, sums = oracle.tabulate(mat)
+    expect = job.tally.times[-1] * sums[1] / sums[0]
+    se = nscat.std(ddof=1) / math.sqrt(job.n_particles)
+    assert abs(nscat.mean() - expect) <= 4 * se, (nscat.mean(), expect, se)
+
+
+# ----------------------------------------------- Gradient problems (C4) ----
+
+def _kappa_bulk(mat):
+    _, Cm, _ = oracle.tabulate(mat)
+    om, dom, dos, vg, tau, deg = mat.flat()
+    return Cm, vg, tau, float(np.sum(Cm * vg * vg * tau) / 3.0)
+
+
+def test_bulk_gradient_gives_bulk_conductivity():
+    """Periodic cell without a pore: kappa = sum C v^2 tau / 3 for any truncation."""
+    mat = di.gray_material()
+    _, _, _, kb = _kappa_bulk(mat)
+    for kmax in (1, 10):
+        job = di.pore_cell(200e-9, 0.0, 100_000, seed=21, material=mat, kmax=kmax, n_hj=0)
+        res, *_ = oracle.simulate(job, threads=THREADS)
+        assert abs(res["kappa"] - kb) <= 4 * res["kappa_se"], (kmax, res["kappa"], kb, res["kappa_se"])
+        assert res["kappa_se"] < 0.03 * kb
+
+
+@pytest.mark.parametrize("p", [0.0, 0.5, 0.9])
+def test_in_plane_film_fuchs_sondheimer_gray(p):
+    """In-plane gray film of thickness = one mean free path: kappa = kappa_bulk S(1, p)."""
+    mat = di.gray_material()
+    Cm, vg, tau, kb = _kappa_bulk(mat)
+    lam = float(vg[0] * tau[0])
+    job = di.in_plane_film(lam, p, 100_000, seed=40, material=mat, kmax=10, n_hj=0)
+    res, *_ = oracle.simulate(job, threads=THREADS)
+    ref = kb * refsol.fuchs_sondheimer_S(1.0, p)
+    assert abs(res["kappa"] - ref) <= 4 * res["kappa_se"], (res["kappa"], ref, res["kappa_se"])
+    assert res["kappa_se"] < 0.03 * ref  # the comparison has teeth
+
+
+def test_in_plane_film_fuchs_sondheimer_silicon():
+    """Frequency-dependent in-plane film: kappa = sum_m (C v^2 tau / 3) S(d / Lambda_m, p)."""
+    mat = di.silicon_like()
+    Cm, vg, tau, kb = _kappa_bulk(mat)
+    d = 100e-9
+    job = di.in_plane_film(d, 0.0, 200_000, seed=41, material=mat, kmax=4, n_hj=0)
+    res, *_ = oracle.simulate(job, threads=THREADS)
+    S = refsol.fuchs_sondheimer_S(d / (vg * tau), 0.0, n=400)
+    ref = float(np.sum(Cm * vg * vg * tau / 3.0 * S))
+    assert abs(res["kappa"] - ref) <= 4 * res["kappa_se"], (res["kappa"], ref, res["kappa_se"])
+    assert res["kappa_se"] < 0.03 * ref
+
+
+def test_film_flux_after_first_event_vanishes():
+    """Diffuse walls and isotropic scattering: the mean contribution after the first
+    scattering event is zero (H_j, j >= 1) and H_0 carries the whole conductivity."""
+    mat = di.gray_material()
+    _, vg, tau, kb = _kappa_bulk(mat)
+    job = di.in_plane_film(float(vg[0] * tau[0]), 0.0, 100_000, seed=42, material=mat, kmax=8, n_hj=8)
+    res, *_ = oracle.simulate(job, threads=THREADS)
+    hj, se = res["hj"], res["hj_se"]
+    assert np.all(np.abs(hj[1:]) <= 4 * se[1:])
+    assert abs(hj.sum() - res["kappa"]) <= 1e-9 * abs(res["kappa"])
+    assert hj[0] > 10 * se[0]
