@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Benchmark: scattering events per second of the deviational phonon Monte Carlo
+hot path on one MI355X.
+
+Workload (one step): the silicon-like frequency-dependent material (1000
+frequency bins per branch, LA + doubly degenerate TA, sine dispersion,
+tau^-1 = A w^4 + B w^2 T exp(-C/T)) in 12 cross-plane films of thicknesses
+log-spaced 10 nm - 10 um between isothermal walls at T_eq +- 0.5 K, 1e8
+particles per film, 20 temperature / heat-flux bins, FP32 flight with FP64
+tallies, all 12 films in ONE persistent launch.  Inputs (material tables,
+job descriptors) are resident on the device before timing starts; every
+particle is generated on the device from (seed, pid).
+
+Printed JSON line: metric/value (scattering events/s), the plain form
+(one FP64 launch per film, one thread per particle, global tables, direct
+FP64 atomics) timed on a subsample of the same workload, the ALU roofline of
+the trajectory kernel from HIP-event timing, and the FP64 CPU oracle timed on a
+bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic VALU work of one flight of the cross-plane slab path, in
+# full-rate lane-operation equivalents (a quarter-rate instruction counts 4):
+#   Philox4x32-10: 10 rounds x (2 32x32->64 multiplies @4 + 2 three-way xors
+#                  + 2 key additions)                                       = 120
+#   three word -> uniform conversions (shift, convert, scale)                =   9
+#   -ln u (log2 @4 + scale), flight time                                     =   6
+#   wall distance, reciprocal @4, hit compare and select                     =  10
+#   position update                                                          =   2
+#   two bin indices (scale, floor, convert, clamp)                           =  10
+#   three FP64 tally accumulations with FP32 -> FP64 conversions             =   9
+#   gain alias draw (shift, mask, compare, select), mu = 2u - 1              =   6
+#   loop control and event bookkeeping                                       =   4
+OPS_PER_FLIGHT = 176
+CU, LANES_PER_CU_CLK, CLOCK = 256, 64, 2.4e9
+PEAK_LANE_OPS = CU * LANES_PER_CU_CLK * CLOCK  # 3.93e13 full-rate VALU lane-ops/s
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(jobs, target_s=15.0):
+    """The FP64 oracle on a bounded sample of every film, all host cores."""
+    import oracle
+
+    threads = os.cpu_count() or 1
+    if "OMP_NUM_THREADS" in os.environ:
+        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+    # calibrate on a small sample, then size the sample to ~target_s
+    def run(n):
+        ev = 0
+        t0 = time.perf_counter()
+        for j in jobs:
+            _, cnt, _ = oracle.run_raw(j, 0, n, threads=threads)
+            ev += cnt["scatters"]
+        return ev, time.perf_counter() - t0
+
+    ev, dt = run(64)
+    n = max(64, int(64 * target_s / max(dt, 1e-3)))
+    n = min(n, 200_000)
+    ev, dt = run(n)
+    return {"value": ev / dt, "unit": "scattering events/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} particles of each of the 12 films ({ev} scattering events, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=float, default=1e8, help="particles per film")
+    ap.add_argument("--plain-n", type=float, default=2e5, help="particles per film for the plain-form sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md"}))
+        sys.exit(2)
+
+    import torch
+
+    import dmc_inputs as di
+    from paper_1206_3316_amd import binding as b
+
+    torch.cuda.set_device(0)
+    mat_in = di.silicon_like()
+    jobs = di.cross_plane_films(n_per_film=int(args.n), material=mat_in)
+    mat = b.Material(mat_in)
+    stream = torch.cuda.current_stream()
+    nbytes = b.workspace_bytes(jobs, mat)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+    def step():
+        r = b.simulate(jobs, material=mat, precision="fp32", form="persistent", stream=stream, workspace=ws)
+        return r, r.stats(-1)
+
+    for i in range(args.warmup):
+        r, st = step()
+        log(f"warmup {i}: {st.scatters:.3e} scatters, kernel {st.kernel_ms:.1f} ms")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    scat = flights = parts = 0
+    kms = []
+    for i in range(args.steps):
+        r, st = step()
+        scat += st.scatters
+        flights += st.iterations
+        parts += st.particles
+        kms.append(st.kernel_ms)
+        log(f"step {i}: {st.scatters:.4e} scatters, {st.iterations:.4e} flights, kernel {st.kernel_ms:.1f} ms")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    value = scat / wall
+    kernel_s = sum(kms) / 1e3
+    achieved = OPS_PER_FLIGHT * flights / kernel_s
+    out = {
+        "metric": "scattering events/s", "value": value, "unit": "scattering events/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 flight / f64 tally", "data": "synthetic",
+        "config": {"workload": "12 silicon-like cross-plane films 10 nm - 10 um, 1e8 particles each "
+                               "(1000 omega bins x LA+2TA, walls T_eq +- 0.5 K, 20 bins), one persistent launch",
+                   "particles_per_step": parts // args.steps},
+        "particles_per_s": parts / wall,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                     "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "kernel": "persistent_kernel<float, GEOM_SLAB>", "ops_per_flight": OPS_PER_FLIGHT,
+                     "kernel_ms_per_step": kernel_s * 1e3 / args.steps},
+    }
+    if not args.no_plain:
+        pjobs = di.cross_plane_films(n_per_film=int(args.plain_n), material=mat_in)
+        rp = b.simulate(pjobs, material=mat, precision="fp64", form="plain", stream=stream)
+        sp = rp.stats(-1)
+        rq = b.simulate(pjobs, material=mat, precision="fp32", form="persistent", stream=stream)
+        sq = rq.stats(-1)
+        plain_rate = sp.scatters / (sp.kernel_ms / 1e3)
+        out["plain_form"] = {"scattering_events_per_s": plain_rate, "sample_particles_per_film": int(args.plain_n),
+                             "kernel_ms": sp.kernel_ms,
+                             "persistent_same_sample_events_per_s": sq.scatters / (sq.kernel_ms / 1e3)}
+        out["vs_plain"] = value / plain_rate
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(jobs)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

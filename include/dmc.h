@@ -1,0 +1,296 @@
+/*
+ * dmc.h -- C ABI of the MI355X library for the linearized energy-based
+ * deviational Monte Carlo method for phonon transport (Peraud &
+ * Hadjiconstantinou, "An alternative approach to efficient simulation of
+ * micro/nanoscale phonon transport").
+ *
+ * The method (the particle algorithm, steps I-VI): under linearized
+ * conditions deviational particles do not interact, so each particle is
+ * simulated on its own.  It is drawn from a source term (initial condition,
+ * isothermal wall, or imposed temperature gradient, Eq. (6)), flies for an
+ * exponentially distributed time with mean tau(omega, p, T_eq) (step II),
+ * meets geometry boundaries (step IVa: isothermal walls absorb, adiabatic
+ * walls reflect specularly or diffusely, periodic faces re-insert), and at a
+ * scattering event (step IVb) is redrawn from the normalised distribution
+ * D de^eq/dT / tau of Eq. (2) with an isotropic direction and an unchanged
+ * sign.  Track-length estimators (Eq. (4); Eq. (3) for snapshots) score
+ * temperature, pseudo-temperature, heat flux and conductivity.
+ *
+ * Conventions for every entry point:
+ *   - every call returns a dmc_status; on error nothing is allocated and any
+ *     out-handle is set to NULL; dmc_last_error() returns a thread-local
+ *     message valid until the next call on that thread;
+ *   - handles are opaque; the caller creates and destroys them; material and
+ *     geometry handles are immutable after creation and may be shared;
+ *   - all arrays passed in are copied or fully consumed before the call
+ *     returns (except a caller-provided device workspace, see dmc_run_opts);
+ *   - SI units: rad/s, s/m^3 per rad/s, m/s, s, K, m, K/m;
+ *   - the library runs on the current HIP device; it needs gfx950.
+ */
+#ifndef DMC_H_
+#define DMC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dmc_status;
+#define DMC_OK 0
+#define DMC_E_INVALID (-1)     /* an argument is out of range or inconsistent */
+#define DMC_E_NOMEM (-2)       /* host or device allocation failed / workspace too small */
+#define DMC_E_DEVICE (-3)      /* a HIP call failed (no device, launch failure, ...) */
+#define DMC_E_UNSUPPORTED (-4) /* valid request this build does not implement */
+#define DMC_E_BUSY (-5)        /* the server cannot admit more work right now */
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char *dmc_last_error(void);
+
+/* Library version string. */
+const char *dmc_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Material: D(omega, p), V_g(omega, p), tau(omega, p, T_eq)  (Eq. (1), (2))  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct dmc_material dmc_material;
+
+/* One polarization branch tabulated on frequency bins.  All arrays have
+ * n_bins entries and are read during the call only. */
+typedef struct {
+    int32_t n_bins;
+    const double *omega;  /* bin centre [rad/s], > 0 */
+    const double *domega; /* bin width [rad/s], >= 0 */
+    const double *dos;    /* density of states per polarization [s/m^3], >= 0 */
+    const double *vg;     /* group-velocity magnitude [m/s], > 0 */
+    const double *tau;    /* relaxation time at T_eq [s], > 0 */
+    double degeneracy;    /* identical polarizations in this branch (TA: 2) */
+} dmc_branch;
+
+/* Tabulates the states m = (bin, branch) in branch order, computes
+ * de^eq/dT(omega, T_eq) and the heat capacities C_m = D de/dT domega g in
+ * FP64, builds the exact-integer alias tables of the initial (~C), wall-flux
+ * (~C v) and post-scattering gain (~C / tau, Eq. (2)) distributions, and
+ * uploads device copies.  Total states must be 1..65536.
+ * Errors: DMC_E_INVALID (non-finite or non-positive inputs), DMC_E_DEVICE. */
+dmc_status dmc_material_create(const dmc_branch *branches, int32_t n_branches, double T_eq, dmc_material **out);
+dmc_status dmc_material_destroy(dmc_material *m);
+
+/* sums[0] = C_tot = sum C_m [J/m^3/K], sums[1] = G_tau = sum C_m / tau_m,
+ * sums[2] = G_v = sum C_m v_m; n_states may be NULL. */
+dmc_status dmc_material_info(const dmc_material *m, int32_t *n_states, double sums[3]);
+
+/* ------------------------------------------------------------------------ */
+/* Geometry (steps III and IVa)                                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct dmc_geometry dmc_geometry;
+
+#define DMC_GEOM_SLAB_Z 0       /* walls at z = 0 (wall[0]) and z = length (wall[1]) */
+#define DMC_GEOM_FILM_X 1       /* walls at x = 0 (wall[0]) and x = length (wall[1]) */
+#define DMC_GEOM_PORE_CELL_XZ 2 /* periodic cell [0,length)^2 in x-z, cylindrical pore
+                                   (axis y) of `radius` at the centre; wall[0] = pore */
+#define DMC_GEOM_HALFSPACE_Z 3  /* solid z >= 0, surface z = 0 described by wall[0] */
+
+#define DMC_WALL_ISOTHERMAL 0 /* absorbs; emits its deviational flux if T != T_eq */
+#define DMC_WALL_ADIABATIC 1  /* specular with probability `specularity`, else diffuse */
+#define DMC_WALL_PERIODIC 2   /* plane pair only: re-insert at the opposite wall */
+
+typedef struct {
+    int32_t type;
+    double temperature; /* isothermal walls [K] */
+    double specularity; /* adiabatic walls, in [0, 1] */
+} dmc_wall;
+
+typedef struct {
+    int32_t kind;
+    double length; /* slab L, film d, cell period P [m] (> 0; unused for the half space) */
+    double radius; /* pore radius [m], 0 <= radius < length / 2 */
+    dmc_wall wall[2];
+} dmc_geometry_desc;
+
+dmc_status dmc_geometry_create(const dmc_geometry_desc *desc, dmc_geometry **out);
+dmc_status dmc_geometry_destroy(dmc_geometry *g);
+
+/* ------------------------------------------------------------------------ */
+/* Sources (step I and the source-term paragraph; Eq. (6))                   */
+/* ------------------------------------------------------------------------ */
+
+#define DMC_SRC_WALLS 0    /* steady: isothermal walls with T != T_eq emit V_g cos C |T - T_eq| */
+#define DMC_SRC_GAUSSIAN 1 /* transient: T_i - T_eq = dT exp(-|x|^2 / radius^2), half space */
+#define DMC_SRC_GRADIENT 2 /* steady: uniform volumetric source of dT/dz = gradient */
+
+typedef struct {
+    int32_t kind;
+    double dT;       /* GAUSSIAN amplitude [K] (non-zero) */
+    double radius;   /* GAUSSIAN radius [m] (> 0) */
+    double gradient; /* GRADIENT dT/dz [K/m] (non-zero) */
+} dmc_source;
+
+/* ------------------------------------------------------------------------ */
+/* Tallies (step V; Eq. (3) and (4))                                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t n_bins;    /* 1-D bins along the confining axis (slab: z, film: x); 0 = none; <= 4096 */
+    int32_t n_batches; /* batch replicas for standard errors, batch = pid mod n_batches; 2..256 */
+    int32_t kmax;      /* stop a particle after kmax scattering events; -1 = never */
+    int32_t n_hj;      /* per-scatter-index flux contributions H_j, j < n_hj (<= kmax); 0 = off */
+    int32_t grid[3];   /* transient snapshot grid cells along x, y, z */
+    double grid_lo[3]; /* snapshot grid bounds [m] */
+    double grid_hi[3];
+} dmc_tally_desc;
+
+/* ------------------------------------------------------------------------ */
+/* Running                                                                    */
+/* ------------------------------------------------------------------------ */
+
+#define DMC_PREC_FP64 0       /* every step in FP64 (the parity mode) */
+#define DMC_PREC_FP32_TALLY64 1 /* flight, intersection, sampling in FP32; tallies in FP64 */
+
+#define DMC_FORM_PLAIN 0      /* one thread per particle run to completion, tables in global
+                                 memory, every contribution a direct FP64 global atomic */
+#define DMC_FORM_PERSISTENT 1 /* persistent waves refilling lanes from a particle queue, tables
+                                 staged in LDS, per-lane bin caches and LDS-privatised tallies */
+
+typedef struct {
+    int32_t precision;     /* DMC_PREC_* */
+    int32_t form;          /* DMC_FORM_* */
+    void *stream;          /* hipStream_t to run on (NULL: the null stream) */
+    int32_t block;         /* persistent: threads per workgroup (64..1024, multiple of 64); 0 = auto */
+    int32_t chunk;         /* persistent: particles a wave takes from the queue at once; 0 = auto */
+    int32_t refill_min;    /* persistent: refill a wave when at least this many lanes are free; 0 = auto */
+    int32_t lds_tally;     /* persistent: 1 = privatise tallies in LDS when they fit, 0 = global */
+    int32_t grid_blocks;   /* persistent: workgroups to launch; 0 = fill the device */
+    void *workspace;       /* optional caller-owned device memory for tallies and queues */
+    size_t workspace_bytes;
+    uint32_t *nscat_out;   /* optional device array: scattering events of every particle,
+                              indexed by the job's pid offset in the launch plus pid */
+} dmc_run_opts;
+
+/* Fills opts with the defaults (FP32 + FP64 tallies, persistent, auto parameters). */
+void dmc_run_opts_default(dmc_run_opts *opts);
+
+/* One simulation in a batched launch. */
+typedef struct {
+    const dmc_material *material; /* all jobs of one launch must share the material */
+    const dmc_geometry *geometry;
+    dmc_source source;
+    dmc_tally_desc tally;
+    uint64_t n_particles; /* >= 1 */
+    uint64_t seed;        /* Philox key */
+    const double *times;  /* transient snapshot times [s], ascending, > 0; NULL for steady */
+    int32_t n_times;      /* <= 1024; the last time is t_final */
+} dmc_job;
+
+typedef struct dmc_result dmc_result;
+
+/* Bytes of device workspace a launch of these jobs needs (tallies, queue, counters). */
+dmc_status dmc_workspace_size(const dmc_job *jobs, int32_t n_jobs, const dmc_run_opts *opts, size_t *bytes);
+
+/* Runs one simulation; asynchronous on opts->stream.  Equivalent to a batch of one. */
+dmc_status dmc_simulate(const dmc_material *material, const dmc_geometry *geometry, const dmc_source *source,
+                        uint64_t n_particles, uint64_t seed, const dmc_tally_desc *tally, const double *times,
+                        int32_t n_times, const dmc_run_opts *opts, dmc_result **out);
+
+/* Runs n_jobs simulations in ONE launch (persistent form: one particle queue
+ * over all jobs; plain form: one launch per job on the same stream).
+ * Asynchronous on opts->stream. */
+dmc_status dmc_simulate_batch(const dmc_job *jobs, int32_t n_jobs, const dmc_run_opts *opts, dmc_result **out);
+
+#define DMC_Q_T 0          /* energy temperature T - T_eq per bin [K] (n = n_bins) */
+#define DMC_Q_TLOC 1       /* pseudo-temperature T_loc - T_eq per bin [K] */
+#define DMC_Q_FLUX 2       /* heat flux along z per bin [W/m^2] */
+#define DMC_Q_KAPPA 3      /* effective conductivity -<q_z> / (dT/dz) [W/m/K] (n = 1) */
+#define DMC_Q_HJ 4         /* conductivity carried between scatter j and j+1 (n = n_hj) */
+#define DMC_Q_SNAPSHOT 5   /* T - T_eq per grid cell at time_index [K] (n = cells, x fastest) */
+#define DMC_Q_SNAPSHOT_SUM 6 /* raw sum of signs per cell at time_index, overflow last (n = cells+1) */
+#define DMC_Q_RAW 7        /* the job's raw FP64 tally block (n = dmc_tally_raw_size) */
+
+/* Waits for the launch, then writes n values of `quantity` of job `job` (and,
+ * if stderr_out is not NULL, their standard errors: batch means for bins,
+ * per-particle moments otherwise) into caller-owned host arrays.
+ * Errors: DMC_E_INVALID (quantity not tallied, n too small, job out of range). */
+dmc_status dmc_tally_read(const dmc_result *res, int32_t job, int32_t quantity, int32_t time_index, double *mean,
+                          double *stderr_out, size_t n);
+
+/* Number of doubles of DMC_Q_RAW for a job. */
+dmc_status dmc_tally_raw_size(const dmc_result *res, int32_t job, size_t *n);
+
+typedef struct {
+    uint64_t particles;  /* particles completed */
+    uint64_t scatters;   /* scattering events (step IVb only) */
+    uint64_t boundary;   /* boundary interactions (step IVa) */
+    uint64_t iterations; /* flights (Philox STEP blocks) */
+    uint64_t capped;     /* particles stopped by the 2^24-flight safety cap */
+    double kernel_ms;    /* device time of the trajectory launch(es), HIP events */
+} dmc_stats;
+
+/* Waits for the launch; job = -1 gives the launch totals. */
+dmc_status dmc_result_stats(const dmc_result *res, int32_t job, dmc_stats *out);
+dmc_status dmc_result_destroy(dmc_result *res);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of simulation requests on one device          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct dmc_server dmc_server;
+
+typedef struct {
+    size_t memory_budget;  /* device bytes the admitted requests' tallies may hold */
+    int32_t max_active;    /* requests resident at once (1..64) */
+    uint64_t epoch_flights; /* estimated flights per epoch launch, shared equally by the admitted
+                               requests (0 = 2e10) */
+    dmc_run_opts run;      /* precision / form / stream / parameters of every epoch */
+} dmc_server_opts;
+
+/* The server admits requests while their device memory fits the budget and
+ * a slot is free; each epoch is one persistent launch over a slice of every
+ * admitted request's particle range, so requests that arrive while others
+ * run join at the next epoch.  A request's tallies stay on the device until
+ * it is collected. */
+dmc_status dmc_server_create(const dmc_material *material, const dmc_server_opts *opts, dmc_server **out);
+/* Queues a request (copied); *ticket identifies it.  DMC_E_INVALID if it can never fit. */
+dmc_status dmc_server_submit(dmc_server *s, const dmc_job *job, uint64_t *ticket);
+/* Runs one epoch if any work is pending (admitting queued requests first).
+ * *n_done receives the number of requests that completed in this epoch. */
+dmc_status dmc_server_step(dmc_server *s, int32_t *n_done);
+/* 1 if the ticket's request is complete, 0 if not (queued or running). */
+dmc_status dmc_server_poll(dmc_server *s, uint64_t ticket, int32_t *done);
+/* Takes a completed request's result (a one-job dmc_result owned by the caller). */
+dmc_status dmc_server_collect(dmc_server *s, uint64_t ticket, dmc_result **out);
+/* Requests queued / running. */
+dmc_status dmc_server_load(const dmc_server *s, int32_t *queued, int32_t *running);
+dmc_status dmc_server_destroy(dmc_server *s);
+
+/* ------------------------------------------------------------------------ */
+/* Test hooks                                                                */
+/* ------------------------------------------------------------------------ */
+
+#define DMC_TAG_STEP 0
+#define DMC_TAG_EMIT_A 1
+#define DMC_TAG_EMIT_B 2
+
+/* Philox4x32-10 block for counter (pid lo, pid hi, k, tag) and key (seed lo,
+ * seed hi); n requests at once (arrays of n, host memory), computed on the
+ * device.  out has 4 n words. */
+dmc_status dmc_debug_philox(uint64_t seed, const uint64_t *pid, const uint32_t *k, const uint32_t *tag,
+                            uint32_t *out, size_t n);
+
+#define DMC_TABLE_GAIN 0 /* ~ C / tau */
+#define DMC_TABLE_INIT 1 /* ~ C */
+#define DMC_TABLE_FLUX 2 /* ~ C v */
+
+/* Canonical alias table (thresh, alias; 2^bits columns) that the library built. */
+dmc_status dmc_debug_alias(const dmc_material *m, int32_t which, int32_t *bits, uint32_t *thresh,
+                           uint32_t *alias, size_t n);
+/* Device lookups of table `which` for n host words; writes the drawn states. */
+dmc_status dmc_debug_alias_draw(const dmc_material *m, int32_t which, const uint32_t *words, uint32_t *states,
+                                size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMC_H_ */

@@ -1,0 +1,960 @@
+// dmc_host.cpp -- host side of the MI355X deviational Monte Carlo library:
+// material tabulation and alias tables, geometry/source/tally validation,
+// launch planning (LDS privatisation, occupancy), result finalisation, the
+// serving loop and the C ABI of include/dmc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dmc_host_internal.h"
+
+using namespace dmc;
+
+namespace dmc {
+
+namespace {
+thread_local std::string g_err;
+}
+
+dmc_status fail(dmc_status code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+}  // namespace dmc
+
+#define HIP_OR_FAIL DMC_HIP_OR_FAIL
+
+namespace {
+
+constexpr double kHbar = 1.054571817e-34;  // J s (CODATA 2018)
+constexpr double kBoltz = 1.380649e-23;    // J/K (CODATA 2018)
+constexpr double kPi = 3.14159265358979323846;
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// ------------------------------------------------------------ alias tables ----
+
+namespace dmc {
+
+// Exact-integer Walker/Vose construction.  Masses: floor((w_j / W) 2^32) with W
+// summed in index order, the shortfall to 2^32 handed out one unit each to the
+// largest fractional parts (lower index first on ties).  Columns of capacity
+// U = 2^(32-b); under-full and over-full columns wait in two FIFO queues in
+// index order; the front under-full column takes its threshold and the front
+// over-full column as alias, which gives up (U - threshold) and rejoins the
+// back of whichever queue it now belongs to; left-over columns are full.
+bool build_alias(const std::vector<double> &w, AliasTable &t, std::string &why)
+{
+    const size_t K = w.size();
+    if (K == 0 || K > 65536) {
+        why = "alias table needs 1..65536 weights";
+        return false;
+    }
+    int b = 1;
+    while ((size_t(1) << b) < K) ++b;
+    const size_t n = size_t(1) << b;
+    double W = 0.0;
+    for (size_t j = 0; j < K; ++j) {
+        if (!finite_nonneg(w[j])) {
+            why = "alias weight is negative or not finite";
+            return false;
+        }
+        W += w[j];
+    }
+    if (!(W > 0.0) || !std::isfinite(W)) {
+        why = "alias weights sum to zero";
+        return false;
+    }
+    std::vector<uint64_t> q(n, 0);
+    std::vector<double> frac(n, 0.0);
+    uint64_t assigned = 0;
+    for (size_t j = 0; j < K; ++j) {
+        const double sc = (w[j] / W) * 4294967296.0;
+        const double fl = std::floor(sc);
+        q[j] = (uint64_t)fl;
+        frac[j] = sc - fl;
+        assigned += q[j];
+    }
+    const uint64_t total = uint64_t(1) << 32;
+    if (assigned > total || total - assigned > n) {
+        why = "alias rounding failed";
+        return false;
+    }
+    std::vector<uint32_t> order(n);
+    for (size_t j = 0; j < n; ++j) order[j] = (uint32_t)j;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return frac[x] > frac[y]; });
+    for (uint64_t r = 0; r < total - assigned; ++r) q[order[r]] += 1;
+
+    t.bits = b;
+    t.mass = q;
+    t.thresh.assign(n, 0);
+    t.alias.assign(n, 0);
+    const uint64_t U = uint64_t(1) << (32 - b);
+    std::deque<uint32_t> under, over;
+    for (size_t j = 0; j < n; ++j) (q[j] < U ? under : over).push_back((uint32_t)j);
+    while (!under.empty() && !over.empty()) {
+        const uint32_t l = under.front();
+        under.pop_front();
+        const uint32_t g = over.front();
+        over.pop_front();
+        t.thresh[l] = (uint32_t)q[l];
+        t.alias[l] = g;
+        q[g] -= (U - q[l]);
+        (q[g] < U ? under : over).push_back(g);
+    }
+    for (uint32_t g : over) {
+        t.thresh[g] = (uint32_t)U;
+        t.alias[g] = g;
+    }
+    for (uint32_t l : under) {
+        t.thresh[l] = (uint32_t)U;
+        t.alias[l] = l;
+    }
+    t.packed.resize(n);
+    for (size_t j = 0; j < n; ++j) t.packed[j] = pack_alias(t.thresh[j], t.alias[j], (uint32_t)j, b);
+    return true;
+}
+
+}  // namespace dmc
+
+// ------------------------------------------------------------------ handles ----
+
+dmc_material::~dmc_material()
+{
+    for (void *p : {(void *)d_gain, (void *)d_init, (void *)d_flux, (void *)d_st32, (void *)d_st64})
+        if (p) (void)hipFree(p);
+}
+
+dmc_result::~dmc_result()
+{
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (dev_mem) (void)hipFree(dev_mem);
+    if (on_destroy) on_destroy();
+}
+
+namespace dmc {
+
+// --------------------------------------------------------- job validation ----
+
+dmc_status prepare_job(const dmc_job &jb, JobHost &h)
+{
+    if (!jb.material || !jb.geometry) return fail(DMC_E_INVALID, "job without material or geometry");
+    const dmc_material &M = *jb.material;
+    const dmc_geometry_desc &g = jb.geometry->d;
+    const dmc_source &s = jb.source;
+    const dmc_tally_desc &t = jb.tally;
+    if (jb.n_particles < 1) return fail(DMC_E_INVALID, "n_particles must be >= 1");
+    if (t.n_bins < 0 || t.n_bins > kMaxBins) return fail(DMC_E_INVALID, "n_bins out of range");
+    if (t.n_batches < 2 || t.n_batches > 256) return fail(DMC_E_INVALID, "n_batches must be 2..256");
+    if (t.kmax < -1) return fail(DMC_E_INVALID, "kmax must be >= -1");
+    if (t.n_hj < 0 || t.n_hj > kMaxHj || (t.n_hj > 0 && (t.kmax < 0 || t.n_hj > t.kmax)))
+        return fail(DMC_E_INVALID, "n_hj must be in 0..kmax");
+    if (jb.n_times < 0 || jb.n_times > kMaxTimes || (jb.n_times > 0 && !jb.times))
+        return fail(DMC_E_INVALID, "bad snapshot times");
+    h.job = jb;
+    h.geom = g;
+    h.times.assign(jb.times, jb.times + jb.n_times);
+    for (int i = 0; i < jb.n_times; ++i)
+        if (!finite_pos(h.times[i]) || (i > 0 && !(h.times[i] > h.times[i - 1])))
+            return fail(DMC_E_INVALID, "snapshot times must be positive and increasing");
+    const bool transient = jb.n_times > 0;
+    JobDev &d = h.dev;
+    std::memset(&d, 0, sizeof(d));
+    d.n = jb.n_particles;
+    d.key0 = (uint32_t)jb.seed;
+    d.key1 = (uint32_t)(jb.seed >> 32);
+    d.geom = g.kind;
+    d.src = s.kind;
+    d.length = g.length;
+    d.radius = g.radius;
+    for (int i = 0; i < 2; ++i) {
+        d.wall_type[i] = g.wall[i].type;
+        const double p = g.wall[i].specularity;
+        d.spec_thr[i] = std::min<uint64_t>((uint64_t)std::llround(p * 4294967296.0), uint64_t(1) << 32);
+    }
+    d.n_bins = t.n_bins;
+    d.n_batches = t.n_batches;
+    d.kmax = t.kmax;
+    d.n_hj = t.n_hj;
+    d.n_times = jb.n_times;
+    d.lds_bins = d.lds_kappa = d.lds_hj = -1;
+    d.off_bins = d.off_kappa = d.off_hj = d.off_snap = d.off_snap_abs = -1;
+    if ((g.kind == DMC_GEOM_SLAB_Z || g.kind == DMC_GEOM_FILM_X) && t.n_bins > 0) {
+        d.bins_per_len = (double)t.n_bins / g.length;
+        d.bin_width = g.length / (double)t.n_bins;
+    } else if (t.n_bins > 0) {
+        return fail(DMC_E_INVALID, "1-D bins need a slab or film geometry");
+    }
+
+    if (s.kind == DMC_SRC_WALLS) {
+        if (g.kind != DMC_GEOM_SLAB_Z && g.kind != DMC_GEOM_FILM_X)
+            return fail(DMC_E_INVALID, "wall sources need a slab or film geometry");
+        if (transient) return fail(DMC_E_UNSUPPORTED, "wall sources are steady (no snapshot times)");
+        double pw[2];
+        int nsrc = 0;
+        for (int i = 0; i < 2; ++i) {
+            d.wall_sign[i] = (g.wall[i].temperature > M.T_eq) ? 1.0 : -1.0;
+            if (g.wall[i].type == DMC_WALL_ISOTHERMAL && g.wall[i].temperature != M.T_eq) {
+                pw[nsrc] = std::fabs(g.wall[i].temperature - M.T_eq) * M.G_v / 4.0;
+                d.src_wall[nsrc] = i;
+                ++nsrc;
+            }
+        }
+        if (nsrc == 0) return fail(DMC_E_INVALID, "no isothermal wall differs from T_eq");
+        d.n_src = nsrc;
+        h.power = (nsrc == 2) ? pw[0] + pw[1] : pw[0];
+        if (nsrc == 2) {
+            AliasTable st;
+            std::string why;
+            if (!build_alias({pw[0], pw[1]}, st, why)) return fail(DMC_E_INVALID, why);
+            d.src_packed[0] = st.packed[0];
+            d.src_packed[1] = st.packed[1];
+        }
+        h.avg_volume = g.length;
+    } else if (s.kind == DMC_SRC_GRADIENT) {
+        if (!(std::isfinite(s.gradient) && s.gradient != 0.0)) return fail(DMC_E_INVALID, "zero gradient");
+        if (transient) return fail(DMC_E_UNSUPPORTED, "gradient sources are steady");
+        double vol;
+        if (g.kind == DMC_GEOM_FILM_X) {
+            vol = g.length;
+            h.avg_volume = g.length;
+        } else if (g.kind == DMC_GEOM_PORE_CELL_XZ) {
+            vol = g.length * g.length - kPi * g.radius * g.radius;
+            h.avg_volume = g.length * g.length;
+        } else {
+            return fail(DMC_E_INVALID, "gradient sources need a film or pore-cell geometry");
+        }
+        h.power = vol * std::fabs(s.gradient) * M.G_v / 2.0;
+        d.sign0 = (s.gradient > 0.0) ? -1.0 : 1.0;
+    } else if (s.kind == DMC_SRC_GAUSSIAN) {
+        if (g.kind != DMC_GEOM_HALFSPACE_Z || !transient)
+            return fail(DMC_E_INVALID, "the gaussian initial condition needs a half space and snapshot times");
+        if (!(std::isfinite(s.dT) && s.dT != 0.0) || !finite_pos(s.radius))
+            return fail(DMC_E_INVALID, "gaussian needs dT != 0 and radius > 0");
+        h.power = M.C_tot * std::fabs(s.dT) * std::pow(kPi, 1.5) * s.radius * s.radius * s.radius / 2.0;
+        d.sign0 = (s.dT > 0.0) ? 1.0 : -1.0;
+        d.sigma = s.radius / std::sqrt(2.0);
+    } else {
+        return fail(DMC_E_INVALID, "unknown source kind");
+    }
+    if (transient) {
+        int64_t nc = 1;
+        for (int i = 0; i < 3; ++i) {
+            if (t.grid[i] < 1 || !(t.grid_hi[i] > t.grid_lo[i]))
+                return fail(DMC_E_INVALID, "snapshot grid needs >= 1 cell and hi > lo per axis");
+            d.grid[i] = t.grid[i];
+            d.grid_lo[i] = t.grid_lo[i];
+            d.grid_ext[i] = t.grid_hi[i] - t.grid_lo[i];
+            nc *= t.grid[i];
+        }
+        if (nc > (int64_t(1) << 31)) return fail(DMC_E_INVALID, "snapshot grid too large");
+        d.ncell = nc;
+    }
+    // tally block layout
+    int64_t o = 0;
+    if (t.n_bins > 0) {
+        d.off_bins = o;
+        o += (int64_t)t.n_batches * 3 * t.n_bins;
+    }
+    if (s.kind == DMC_SRC_GRADIENT) {
+        d.off_kappa = o;
+        o += 2;
+        if (t.n_hj > 0) {
+            d.off_hj = o;
+            o += 2 * (int64_t)t.n_hj;
+        }
+    }
+    if (transient) {
+        d.off_snap = o;
+        o += (int64_t)jb.n_times * (d.ncell + 1);
+        d.off_snap_abs = o;
+        o += (int64_t)jb.n_times * (d.ncell + 1);
+    }
+    h.size = o;
+    return DMC_OK;
+}
+
+dmc_status run_opts_check(const dmc_run_opts &o)
+{
+    if (o.precision != DMC_PREC_FP64 && o.precision != DMC_PREC_FP32_TALLY64)
+        return fail(DMC_E_INVALID, "unknown precision");
+    if (o.form != DMC_FORM_PLAIN && o.form != DMC_FORM_PERSISTENT) return fail(DMC_E_INVALID, "unknown form");
+    if (o.block != 0 && (o.block < 64 || o.block > 1024 || o.block % 64 != 0))
+        return fail(DMC_E_INVALID, "block must be a multiple of 64 in 64..1024");
+    if (o.chunk < 0 || o.refill_min < 0 || o.refill_min > 64 || o.grid_blocks < 0)
+        return fail(DMC_E_INVALID, "negative chunk / refill_min / grid_blocks");
+    return DMC_OK;
+}
+
+namespace {
+
+int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+    return cus;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------- launch plan ----
+
+dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, const std::vector<double> &times,
+                          const LaunchBuffers &b, size_t tally_doubles, bool zero_tally, const dmc_run_opts &o,
+                          hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    const int n_jobs = (int)devs.size();
+    bool slab_only = true;
+    for (auto &d : devs)
+        if (d.geom != GEOM_SLAB || d.src != SRC_WALLS || d.n_times > 0) slab_only = false;
+    KArgs a{};
+    a.jobs = b.jobs;
+    a.n_jobs = n_jobs;
+    a.K = M->K;
+    a.qbegin = 0;
+    a.total = 0;
+    for (auto &d : devs) a.total += d.n;
+    a.queue = b.queue;
+    a.gain_bits = M->gain.bits;
+    a.flux_bits = M->flux.bits;
+    a.init_bits = M->init.bits;
+    a.gain_packed = M->d_gain;
+    a.flux_packed = M->d_flux;
+    a.init_packed = M->d_init;
+    a.st32 = M->d_st32;
+    a.st64 = M->d_st64;
+    a.tally = b.tally;
+    a.times = b.times;
+    a.nscat_out = o.nscat_out;
+    a.stats = b.stats;
+    a.kpad = 1 << M->gain.bits;
+    a.lds_stats = (n_jobs <= kLdsStatJobs) ? 1 : 0;
+    const size_t stats_lds = a.lds_stats ? (size_t)n_jobs * kStats * 8 : 0;
+    for (auto &d : devs) d.lds_bins = d.lds_kappa = d.lds_hj = -1;
+    int block = 256, grid = 1;
+    size_t lds_bytes = 0;
+    if (o.form == DMC_FORM_PERSISTENT) {
+        // LDS: gain table + per-state data, then privatised tallies while they fit
+        const size_t tab = (((size_t)a.kpad * 4 + 15) & ~size_t(15)) + (size_t)M->K * 16;
+        const size_t cap = (size_t)max_lds_bytes();
+        if (tab + stats_lds + 1024 > cap)
+            return fail(DMC_E_UNSUPPORTED, "persistent form: material tables do not fit in LDS");
+        const size_t budget = (cap - tab - stats_lds - 16) / 8;  // doubles
+        int32_t lo = 0;
+        if (o.lds_tally) {
+            for (auto &d : devs) {
+                if (d.off_bins >= 0) {
+                    const int32_t n = d.n_batches * 3 * d.n_bins;
+                    if ((size_t)(lo + n) <= budget) {
+                        d.lds_bins = lo;
+                        lo += n;
+                    }
+                }
+                if (d.off_kappa >= 0 && (size_t)(lo + 2) <= budget) {
+                    d.lds_kappa = lo;
+                    lo += 2;
+                }
+                if (d.off_hj >= 0 && (size_t)(lo + 2 * d.n_hj) <= budget) {
+                    d.lds_hj = lo;
+                    lo += 2 * d.n_hj;
+                }
+            }
+        }
+        a.lds_tally_doubles = lo;
+        lds_bytes = ((tab + 15) & ~size_t(15)) + (size_t)lo * 8 + stats_lds;
+        a.chunk = o.chunk > 0 ? o.chunk : 1024;
+        a.refill_min = o.refill_min > 0 ? o.refill_min : 16;
+        block = o.block > 0 ? o.block : (lds_bytes > 64 * 1024 ? 1024 : 512);
+        const int per_cu = occupancy_blocks(o.precision, o.form, slab_only, block, lds_bytes);
+        grid = o.grid_blocks > 0 ? o.grid_blocks : device_cus() * per_cu;
+    } else {
+        a.lds_tally_doubles = 0;
+        a.chunk = 0;
+        a.refill_min = 64;
+        lds_bytes = stats_lds;
+    }
+    DMC_HIP_OR_FAIL(hipMemcpyAsync(b.jobs, devs.data(), devs.size() * sizeof(JobDev), hipMemcpyHostToDevice, s));
+    if (!times.empty())
+        DMC_HIP_OR_FAIL(hipMemcpyAsync(b.times, times.data(), times.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    DMC_HIP_OR_FAIL(launch_fill(zero_tally ? b.tally : nullptr, zero_tally ? tally_doubles : 0, b.stats,
+                                (size_t)n_jobs * kStats, s));
+    DMC_HIP_OR_FAIL(launch_fill(nullptr, 0, b.queue, 2, s));
+    DMC_HIP_OR_FAIL(hipEventRecord(ev0, s));
+    if (o.form == DMC_FORM_PERSISTENT) {
+        DMC_HIP_OR_FAIL(launch_trajectories(a, o.precision, o.form, slab_only, block, grid, lds_bytes, s));
+    } else {
+        // one launch per simulation, in order, on the same stream
+        for (int i = 0; i < n_jobs; ++i) {
+            KArgs aj = a;
+            aj.qbegin = devs[i].base;
+            aj.total = devs[i].base + devs[i].n;
+            const uint64_t blocks = (devs[i].n + 255) / 256;
+            if (blocks > 0x7fffffffull) return fail(DMC_E_INVALID, "too many particles for one plain launch");
+            const bool slab = (devs[i].geom == GEOM_SLAB && devs[i].src == SRC_WALLS && devs[i].n_times == 0);
+            DMC_HIP_OR_FAIL(launch_trajectories(aj, o.precision, o.form, slab, 256, (int)blocks, lds_bytes, s));
+        }
+    }
+    DMC_HIP_OR_FAIL(hipEventRecord(ev1, s));
+    return DMC_OK;
+}
+
+}  // namespace dmc
+
+extern "C" void dmc_run_opts_default(dmc_run_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = DMC_PREC_FP32_TALLY64;
+    o->form = DMC_FORM_PERSISTENT;
+    o->lds_tally = 1;
+}
+
+namespace {
+
+struct Layout {
+    size_t jobs_off, times_off, tally_off, stats_off, queue_off, total;
+    size_t tally_doubles, n_times;
+};
+
+Layout layout_of(const std::vector<JobHost> &jh)
+{
+    Layout L{};
+    size_t o = 0;
+    L.jobs_off = o;
+    o = align256(o + jh.size() * sizeof(JobDev));
+    L.n_times = 0;
+    for (auto &h : jh) L.n_times += h.times.size();
+    L.times_off = o;
+    o = align256(o + std::max<size_t>(L.n_times, 1) * sizeof(double));
+    L.tally_doubles = 0;
+    for (auto &h : jh) L.tally_doubles += (size_t)h.size;
+    L.tally_off = o;
+    o = align256(o + std::max<size_t>(L.tally_doubles, 1) * sizeof(double));
+    L.stats_off = o;
+    o = align256(o + jh.size() * kStats * sizeof(unsigned long long));
+    L.queue_off = o;
+    o = align256(o + 2 * sizeof(unsigned long long));
+    L.total = o;
+    return L;
+}
+
+dmc_status gather_jobs(const dmc_job *jobs, int32_t n_jobs, std::vector<JobHost> &jh)
+{
+    if (!jobs || n_jobs < 1 || n_jobs > kMaxJobs) return fail(DMC_E_INVALID, "n_jobs must be 1..4096");
+    jh.resize(n_jobs);
+    const dmc_material *M = jobs[0].material;
+    uint64_t base = 0;
+    int64_t toff = 0, tim = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        if (jobs[i].material != M) return fail(DMC_E_INVALID, "all jobs of a launch must share one material");
+        dmc_status st = prepare_job(jobs[i], jh[i]);
+        if (st != DMC_OK) return st;
+        JobDev &d = jh[i].dev;
+        if (base + d.n < base) return fail(DMC_E_INVALID, "particle count overflow");
+        d.base = base;
+        d.pid0 = 0;
+        base += d.n;
+        if (d.off_bins >= 0) d.off_bins += toff;
+        if (d.off_kappa >= 0) d.off_kappa += toff;
+        if (d.off_hj >= 0) d.off_hj += toff;
+        if (d.off_snap >= 0) d.off_snap += toff;
+        if (d.off_snap_abs >= 0) d.off_snap_abs += toff;
+        toff += jh[i].size;
+        d.times_off = (int32_t)tim;
+        tim += (int64_t)jh[i].times.size();
+    }
+    return DMC_OK;
+}
+
+dmc_status launch(std::vector<JobHost> &jh, const dmc_run_opts &o, dmc_result **out)
+{
+    *out = nullptr;
+    const dmc_material *M = jh[0].job.material;
+    int dev = 0;
+    HIP_OR_FAIL(hipGetDevice(&dev));
+    if (dev != M->device) return fail(DMC_E_INVALID, "material was created on another device");
+    std::unique_ptr<dmc_result> R(new (std::nothrow) dmc_result());
+    if (!R) return fail(DMC_E_NOMEM, "host allocation failed");
+    R->mat = M;
+    R->stream = (hipStream_t)o.stream;
+    const Layout L = layout_of(jh);
+    char *base = nullptr;
+    if (o.workspace) {
+        if (o.workspace_bytes < L.total)
+            return fail(DMC_E_NOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+        if (((uintptr_t)o.workspace) % 256 != 0) return fail(DMC_E_INVALID, "workspace must be 256-byte aligned");
+        base = (char *)o.workspace;
+    } else {
+        if (hipMalloc(&R->dev_mem, L.total) != hipSuccess) {
+            (void)hipGetLastError();
+            R->dev_mem = nullptr;
+            return fail(DMC_E_NOMEM, "hipMalloc of " + std::to_string(L.total) + " bytes failed");
+        }
+        base = (char *)R->dev_mem;
+    }
+    LaunchBuffers b;
+    b.jobs = (JobDev *)(base + L.jobs_off);
+    b.times = (double *)(base + L.times_off);
+    b.tally = (double *)(base + L.tally_off);
+    b.stats = (unsigned long long *)(base + L.stats_off);
+    b.queue = (unsigned long long *)(base + L.queue_off);
+    R->d_tally = b.tally;
+    R->d_stats = b.stats;
+    R->tally_doubles = L.tally_doubles;
+    std::vector<JobDev> devs(jh.size());
+    std::vector<double> times;
+    for (size_t i = 0; i < jh.size(); ++i) {
+        devs[i] = jh[i].dev;
+        times.insert(times.end(), jh[i].times.begin(), jh[i].times.end());
+    }
+    HIP_OR_FAIL(hipEventCreate(&R->ev0));
+    HIP_OR_FAIL(hipEventCreate(&R->ev1));
+    dmc_status st = enqueue_launch(M, devs, times, b, L.tally_doubles, true, o, R->stream, R->ev0, R->ev1);
+    if (st != DMC_OK) {
+        (void)hipStreamSynchronize(R->stream);
+        return st;
+    }
+    for (size_t i = 0; i < jh.size(); ++i) jh[i].dev = devs[i];
+    R->jobs = std::move(jh);
+    *out = R.release();
+    return DMC_OK;
+}
+
+dmc_status sync_result(dmc_result *R)
+{
+    if (R->synced) return DMC_OK;
+    HIP_OR_FAIL(hipEventSynchronize(R->ev1));
+    float ms = 0.0f;
+    HIP_OR_FAIL(hipEventElapsedTime(&ms, R->ev0, R->ev1));
+    R->kernel_ms = ms;
+    R->h_tally.assign(std::max<size_t>(R->tally_doubles, 1), 0.0);
+    HIP_OR_FAIL(hipMemcpy(R->h_tally.data(), R->d_tally, R->tally_doubles * sizeof(double), hipMemcpyDeviceToHost));
+    R->h_stats.assign(R->jobs.size() * kStats, 0ull);
+    HIP_OR_FAIL(hipMemcpy(R->h_stats.data(), R->d_stats, R->h_stats.size() * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost));
+    R->synced = true;
+    return DMC_OK;
+}
+
+}  // namespace
+
+extern "C" dmc_status dmc_workspace_size(const dmc_job *jobs, int32_t n_jobs, const dmc_run_opts *opts, size_t *bytes)
+{
+    if (!bytes) return fail(DMC_E_INVALID, "bytes is NULL");
+    *bytes = 0;
+    std::vector<JobHost> jh;
+    dmc_status st = gather_jobs(jobs, n_jobs, jh);
+    if (st != DMC_OK) return st;
+    *bytes = layout_of(jh).total;
+    (void)opts;
+    return DMC_OK;
+}
+
+// ------------------------------------------------------------------- C ABI ----
+
+extern "C" const char *dmc_last_error(void) { return dmc::g_err.c_str(); }
+extern "C" const char *dmc_version(void) { return "dmc 0.1 gfx950"; }
+
+extern "C" dmc_status dmc_material_create(const dmc_branch *br, int32_t nbr, double T_eq, dmc_material **out)
+{
+    if (!out) return fail(DMC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!br || nbr < 1) return fail(DMC_E_INVALID, "need at least one branch");
+    if (!finite_pos(T_eq)) return fail(DMC_E_INVALID, "T_eq must be positive");
+    std::unique_ptr<dmc_material> M(new (std::nothrow) dmc_material());
+    if (!M) return fail(DMC_E_NOMEM, "host allocation failed");
+    M->T_eq = T_eq;
+    std::vector<double> wg, wi, wf;
+    for (int b = 0; b < nbr; ++b) {
+        const dmc_branch &B = br[b];
+        if (B.n_bins < 1 || !B.omega || !B.domega || !B.dos || !B.vg || !B.tau)
+            return fail(DMC_E_INVALID, "branch " + std::to_string(b) + " is empty or has NULL arrays");
+        if (!finite_nonneg(B.degeneracy)) return fail(DMC_E_INVALID, "bad degeneracy");
+        for (int i = 0; i < B.n_bins; ++i) {
+            if (!finite_pos(B.omega[i]) || !finite_nonneg(B.domega[i]) || !finite_nonneg(B.dos[i]) ||
+                !finite_pos(B.vg[i]) || !finite_pos(B.tau[i]))
+                return fail(DMC_E_INVALID, "branch " + std::to_string(b) + " bin " + std::to_string(i) +
+                                               " has a non-physical value");
+            // de^eq/dT of hbar w / (exp(hbar w / k_B T) - 1), then C = D de/dT dw g
+            const double x = (kHbar * B.omega[i]) / (kBoltz * T_eq);
+            const double ex = std::exp(x);
+            const double em1 = std::expm1(x);
+            const double dedT = kBoltz * x * x * ex / (em1 * em1);
+            const double C = ((B.dos[i] * dedT) * B.domega[i]) * B.degeneracy;
+            M->v.push_back(B.vg[i]);
+            M->tau.push_back(B.tau[i]);
+            M->C.push_back(C);
+            M->C_tot += C;
+            M->G_tau += C / B.tau[i];
+            M->G_v += C * B.vg[i];
+            wg.push_back(C / B.tau[i]);
+            wi.push_back(C);
+            wf.push_back(C * B.vg[i]);
+        }
+    }
+    M->K = (int32_t)M->v.size();
+    if (M->K > 65536) return fail(DMC_E_INVALID, "more than 65536 states");
+    std::string why;
+    if (!build_alias(wg, M->gain, why) || !build_alias(wi, M->init, why) || !build_alias(wf, M->flux, why))
+        return fail(DMC_E_INVALID, "material: " + why);
+    HIP_OR_FAIL(hipGetDevice(&M->device));
+    std::vector<float4> s32(M->K);
+    std::vector<double2> s64(M->K);
+    for (int m = 0; m < M->K; ++m) {
+        s32[m] = make_float4((float)M->v[m], (float)M->tau[m], (float)(1.0 / M->tau[m]), 0.0f);
+        s64[m] = make_double2(M->v[m], M->tau[m]);
+    }
+    auto up = [&](void **dst, const void *src, size_t bytes) -> dmc_status {
+        if (hipMalloc(dst, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(DMC_E_NOMEM, "hipMalloc failed");
+        }
+        HIP_OR_FAIL(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+        return DMC_OK;
+    };
+    dmc_status st;
+    if ((st = up((void **)&M->d_gain, M->gain.packed.data(), M->gain.packed.size() * 4)) != DMC_OK) return st;
+    if ((st = up((void **)&M->d_init, M->init.packed.data(), M->init.packed.size() * 4)) != DMC_OK) return st;
+    if ((st = up((void **)&M->d_flux, M->flux.packed.data(), M->flux.packed.size() * 4)) != DMC_OK) return st;
+    if ((st = up((void **)&M->d_st32, s32.data(), s32.size() * sizeof(float4))) != DMC_OK) return st;
+    if ((st = up((void **)&M->d_st64, s64.data(), s64.size() * sizeof(double2))) != DMC_OK) return st;
+    *out = M.release();
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_material_destroy(dmc_material *m)
+{
+    delete m;
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_material_info(const dmc_material *m, int32_t *n_states, double sums[3])
+{
+    if (!m) return fail(DMC_E_INVALID, "material is NULL");
+    if (n_states) *n_states = m->K;
+    if (sums) {
+        sums[0] = m->C_tot;
+        sums[1] = m->G_tau;
+        sums[2] = m->G_v;
+    }
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_geometry_create(const dmc_geometry_desc *d, dmc_geometry **out)
+{
+    if (!out) return fail(DMC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!d) return fail(DMC_E_INVALID, "desc is NULL");
+    if (d->kind < DMC_GEOM_SLAB_Z || d->kind > DMC_GEOM_HALFSPACE_Z) return fail(DMC_E_INVALID, "unknown geometry");
+    if (d->kind != DMC_GEOM_HALFSPACE_Z && !finite_pos(d->length)) return fail(DMC_E_INVALID, "length must be > 0");
+    if (d->kind == DMC_GEOM_PORE_CELL_XZ && !(finite_nonneg(d->radius) && d->radius < 0.5 * d->length))
+        return fail(DMC_E_INVALID, "pore radius must be in [0, length/2)");
+    const int nw = (d->kind == DMC_GEOM_SLAB_Z || d->kind == DMC_GEOM_FILM_X) ? 2 : 1;
+    for (int i = 0; i < nw; ++i) {
+        const dmc_wall &w = d->wall[i];
+        if (w.type < DMC_WALL_ISOTHERMAL || w.type > DMC_WALL_PERIODIC) return fail(DMC_E_INVALID, "unknown wall type");
+        if (w.type == DMC_WALL_ADIABATIC && !(w.specularity >= 0.0 && w.specularity <= 1.0))
+            return fail(DMC_E_INVALID, "specularity must be in [0, 1]");
+        if (w.type == DMC_WALL_ISOTHERMAL && !finite_pos(w.temperature))
+            return fail(DMC_E_INVALID, "isothermal wall temperature must be > 0");
+        if (w.type == DMC_WALL_PERIODIC && nw != 2) return fail(DMC_E_INVALID, "periodic walls need a plane pair");
+        if (w.type != DMC_WALL_ADIABATIC && nw == 1) return fail(DMC_E_INVALID, "pore / half-space surface must be adiabatic");
+    }
+    if (nw == 2 && ((d->wall[0].type == DMC_WALL_PERIODIC) != (d->wall[1].type == DMC_WALL_PERIODIC)))
+        return fail(DMC_E_INVALID, "periodic walls come in pairs");
+    dmc_geometry *g = new (std::nothrow) dmc_geometry();
+    if (!g) return fail(DMC_E_NOMEM, "host allocation failed");
+    g->d = *d;
+    if (nw == 1) g->d.wall[1] = g->d.wall[0];
+    *out = g;
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_geometry_destroy(dmc_geometry *g)
+{
+    delete g;
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_simulate_batch(const dmc_job *jobs, int32_t n_jobs, const dmc_run_opts *opts,
+                                         dmc_result **out)
+{
+    if (!out) return fail(DMC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    dmc_run_opts o;
+    if (opts)
+        o = *opts;
+    else
+        dmc_run_opts_default(&o);
+    dmc_status st = run_opts_check(o);
+    if (st != DMC_OK) return st;
+    std::vector<JobHost> jh;
+    if ((st = gather_jobs(jobs, n_jobs, jh)) != DMC_OK) return st;
+    return launch(jh, o, out);
+}
+
+extern "C" dmc_status dmc_simulate(const dmc_material *material, const dmc_geometry *geometry,
+                                   const dmc_source *source, uint64_t n_particles, uint64_t seed,
+                                   const dmc_tally_desc *tally, const double *times, int32_t n_times,
+                                   const dmc_run_opts *opts, dmc_result **out)
+{
+    if (!source || !tally) {
+        if (out) *out = nullptr;
+        return fail(DMC_E_INVALID, "source / tally is NULL");
+    }
+    dmc_job j;
+    j.material = material;
+    j.geometry = geometry;
+    j.source = *source;
+    j.tally = *tally;
+    j.n_particles = n_particles;
+    j.seed = seed;
+    j.times = times;
+    j.n_times = n_times;
+    return dmc_simulate_batch(&j, 1, opts, out);
+}
+
+extern "C" dmc_status dmc_tally_raw_size(const dmc_result *res, int32_t job, size_t *n)
+{
+    if (!res || !n || job < 0 || job >= (int32_t)res->jobs.size()) return fail(DMC_E_INVALID, "bad result / job");
+    *n = (size_t)res->jobs[job].size;
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_tally_read(const dmc_result *cres, int32_t job, int32_t q, int32_t time_index, double *mean,
+                                     double *se, size_t n)
+{
+    dmc_result *R = const_cast<dmc_result *>(cres);
+    if (!R || !mean || job < 0 || job >= (int32_t)R->jobs.size()) return fail(DMC_E_INVALID, "bad result / job");
+    dmc_status st = sync_result(R);
+    if (st != DMC_OK) return st;
+    const JobHost &h = R->jobs[job];
+    const JobDev &d = h.dev;
+    const dmc_material &M = *R->mat;
+    const double N = (double)d.n;
+    // all offsets are relative to the launch's tally buffer
+    const double *T = R->h_tally.data();
+    if (q == DMC_Q_T || q == DMC_Q_TLOC || q == DMC_Q_FLUX) {
+        if (d.off_bins < 0) return fail(DMC_E_INVALID, "no bins tallied");
+        if (n < (size_t)d.n_bins) return fail(DMC_E_INVALID, "output too small");
+        const int qi = q == DMC_Q_T ? 0 : (q == DMC_Q_TLOC ? 1 : 2);
+        const double dz = h.geom.length / d.n_bins;
+        const double norm = (qi == 0 ? 1.0 / M.C_tot : (qi == 1 ? 1.0 / M.G_tau : 1.0)) * h.power / dz;
+        const int B = d.n_batches;
+        for (int k = 0; k < d.n_bins; ++k) {
+            double tot = 0.0;
+            std::vector<double> per;
+            for (int b = 0; b < B; ++b) {
+                const double v = T[d.off_bins + ((int64_t)b * 3 + qi) * d.n_bins + k];
+                tot += v;
+                const double nb = (d.n > (uint64_t)b) ? (double)((d.n - b + B - 1) / B) : 0.0;
+                if (nb > 0) per.push_back(v * norm / nb);
+            }
+            mean[k] = tot * norm / N;
+            if (se) {
+                const size_t m = per.size();
+                if (m < 2) {
+                    se[k] = NAN;
+                } else {
+                    double mu = 0.0;
+                    for (double x : per) mu += x;
+                    mu /= (double)m;
+                    double var = 0.0;
+                    for (double x : per) var += (x - mu) * (x - mu);
+                    var /= (double)(m - 1);
+                    se[k] = std::sqrt(var / (double)m);
+                }
+            }
+        }
+        return DMC_OK;
+    }
+    if (q == DMC_Q_KAPPA || q == DMC_Q_HJ) {
+        if (d.off_kappa < 0) return fail(DMC_E_INVALID, "conductivity needs a gradient source");
+        const double f = h.power / (h.avg_volume * h.job.source.gradient);
+        auto one = [&](double s1, double s2, double *m_out, double *se_out) {
+            const double m = s1 / N;
+            const double var = std::max(s2 / N - m * m, 0.0);
+            *m_out = -f * m;
+            if (se_out) *se_out = std::fabs(f) * std::sqrt(var / std::max(N - 1.0, 1.0));
+        };
+        if (q == DMC_Q_KAPPA) {
+            if (n < 1) return fail(DMC_E_INVALID, "output too small");
+            one(T[d.off_kappa], T[d.off_kappa + 1], mean, se);
+            return DMC_OK;
+        }
+        if (d.off_hj < 0) return fail(DMC_E_INVALID, "H_j not tallied");
+        if (n < (size_t)d.n_hj) return fail(DMC_E_INVALID, "output too small");
+        for (int j = 0; j < d.n_hj; ++j) one(T[d.off_hj + j], T[d.off_hj + d.n_hj + j], mean + j, se ? se + j : nullptr);
+        return DMC_OK;
+    }
+    if (q == DMC_Q_SNAPSHOT || q == DMC_Q_SNAPSHOT_SUM) {
+        if (d.off_snap < 0) return fail(DMC_E_INVALID, "no snapshots tallied");
+        if (time_index < 0 || time_index >= d.n_times) return fail(DMC_E_INVALID, "time_index out of range");
+        const int64_t nc = d.ncell;
+        const double *S = T + d.off_snap + (int64_t)time_index * (nc + 1);
+        const double *A = T + d.off_snap_abs + (int64_t)time_index * (nc + 1);
+        if (q == DMC_Q_SNAPSHOT_SUM) {
+            if (n < (size_t)(nc + 1)) return fail(DMC_E_INVALID, "output too small");
+            for (int64_t c = 0; c <= nc; ++c) {
+                mean[c] = S[c];
+                if (se) se[c] = A[c];
+            }
+            return DMC_OK;
+        }
+        if (n < (size_t)nc) return fail(DMC_E_INVALID, "output too small");
+        double vcell = 1.0;
+        for (int i = 0; i < 3; ++i) vcell *= d.grid_ext[i] / d.grid[i];
+        const double e_eff = h.power / N;
+        const double sc = e_eff / (vcell * M.C_tot);
+        for (int64_t c = 0; c < nc; ++c) {
+            mean[c] = sc * S[c];
+            if (se) {
+                const double m = S[c] / N;
+                const double var = std::max(A[c] / N - m * m, 0.0);
+                se[c] = sc * std::sqrt(N * var);
+            }
+        }
+        return DMC_OK;
+    }
+    if (q == DMC_Q_RAW) {
+        if (n < (size_t)h.size) return fail(DMC_E_INVALID, "output too small");
+        const int64_t first = (d.off_bins >= 0)    ? d.off_bins
+                              : (d.off_kappa >= 0) ? d.off_kappa
+                              : (d.off_snap >= 0)  ? d.off_snap
+                                                   : -1;
+        if (first >= 0) std::memcpy(mean, T + first, (size_t)h.size * sizeof(double));
+        return DMC_OK;
+    }
+    return fail(DMC_E_INVALID, "unknown quantity");
+}
+
+extern "C" dmc_status dmc_result_stats(const dmc_result *cres, int32_t job, dmc_stats *out)
+{
+    dmc_result *R = const_cast<dmc_result *>(cres);
+    if (!R || !out || job < -1 || job >= (int32_t)R->jobs.size()) return fail(DMC_E_INVALID, "bad result / job");
+    dmc_status st = sync_result(R);
+    if (st != DMC_OK) return st;
+    std::memset(out, 0, sizeof(*out));
+    const int j0 = job < 0 ? 0 : job, j1 = job < 0 ? (int)R->jobs.size() : job + 1;
+    for (int j = j0; j < j1; ++j) {
+        const unsigned long long *s = R->h_stats.data() + (size_t)j * kStats;
+        out->particles += s[0];
+        out->scatters += s[1];
+        out->boundary += s[2];
+        out->iterations += s[3];
+        out->capped += s[4];
+    }
+    out->kernel_ms = R->kernel_ms;
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_result_destroy(dmc_result *res)
+{
+    if (res && !res->synced && res->ev1) (void)hipEventSynchronize(res->ev1);
+    delete res;
+    return DMC_OK;
+}
+
+// ---------------------------------------------------------------- test hooks ----
+
+extern "C" dmc_status dmc_debug_philox(uint64_t seed, const uint64_t *pid, const uint32_t *k, const uint32_t *tag,
+                                       uint32_t *out, size_t n)
+{
+    if (!pid || !k || !tag || !out) return fail(DMC_E_INVALID, "NULL argument");
+    if (n == 0) return DMC_OK;
+    uint64_t *dp = nullptr;
+    uint32_t *dk = nullptr, *dt = nullptr, *dout = nullptr;
+    auto cleanup = [&]() {
+        (void)hipFree(dp);
+        (void)hipFree(dk);
+        (void)hipFree(dt);
+        (void)hipFree(dout);
+    };
+    if (hipMalloc(&dp, n * 8) != hipSuccess || hipMalloc(&dk, n * 4) != hipSuccess || hipMalloc(&dt, n * 4) != hipSuccess ||
+        hipMalloc(&dout, n * 16) != hipSuccess) {
+        cleanup();
+        return fail(DMC_E_NOMEM, "hipMalloc failed");
+    }
+    hipError_t e = hipMemcpy(dp, pid, n * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dk, k, n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dt, tag, n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_debug_philox(seed, dp, dk, dt, dout, n, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, dout, n * 16, hipMemcpyDeviceToHost);
+    cleanup();
+    if (e != hipSuccess) return fail(DMC_E_DEVICE, hipGetErrorString(e));
+    return DMC_OK;
+}
+
+namespace {
+const AliasTable *table_of(const dmc_material *m, int32_t which, const uint32_t **dev)
+{
+    if (which == DMC_TABLE_GAIN) {
+        *dev = m->d_gain;
+        return &m->gain;
+    }
+    if (which == DMC_TABLE_INIT) {
+        *dev = m->d_init;
+        return &m->init;
+    }
+    if (which == DMC_TABLE_FLUX) {
+        *dev = m->d_flux;
+        return &m->flux;
+    }
+    return nullptr;
+}
+}  // namespace
+
+extern "C" dmc_status dmc_debug_alias(const dmc_material *m, int32_t which, int32_t *bits, uint32_t *thresh,
+                                      uint32_t *alias, size_t n)
+{
+    if (!m) return fail(DMC_E_INVALID, "material is NULL");
+    const uint32_t *dev;
+    const AliasTable *t = table_of(m, which, &dev);
+    if (!t) return fail(DMC_E_INVALID, "unknown table");
+    if (bits) *bits = t->bits;
+    const size_t cols = t->thresh.size();
+    if ((thresh || alias) && n < cols) return fail(DMC_E_INVALID, "output too small");
+    if (thresh) std::memcpy(thresh, t->thresh.data(), cols * 4);
+    if (alias) std::memcpy(alias, t->alias.data(), cols * 4);
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_debug_alias_draw(const dmc_material *m, int32_t which, const uint32_t *words,
+                                           uint32_t *states, size_t n)
+{
+    if (!m || !words || !states) return fail(DMC_E_INVALID, "NULL argument");
+    const uint32_t *dev;
+    const AliasTable *t = table_of(m, which, &dev);
+    if (!t) return fail(DMC_E_INVALID, "unknown table");
+    if (n == 0) return DMC_OK;
+    uint32_t *dw = nullptr, *ds = nullptr;
+    if (hipMalloc(&dw, n * 4) != hipSuccess || hipMalloc(&ds, n * 4) != hipSuccess) {
+        (void)hipFree(dw);
+        (void)hipFree(ds);
+        return fail(DMC_E_NOMEM, "hipMalloc failed");
+    }
+    hipError_t e = hipMemcpy(dw, words, n * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_debug_alias(dev, t->bits, dw, ds, n, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(states, ds, n * 4, hipMemcpyDeviceToHost);
+    (void)hipFree(dw);
+    (void)hipFree(ds);
+    if (e != hipSuccess) return fail(DMC_E_DEVICE, hipGetErrorString(e));
+    return DMC_OK;
+}

@@ -1,0 +1,99 @@
+// Host-side internals shared by dmc_host.cpp and dmc_server.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../include/dmc.h"
+#include "dmc_internal.h"
+
+namespace dmc {
+
+dmc_status fail(dmc_status code, const std::string &msg);
+
+#define DMC_HIP_OR_FAIL(expr)                                                                                   \
+    do {                                                                                                        \
+        hipError_t e_ = (expr);                                                                                 \
+        if (e_ != hipSuccess) return ::dmc::fail(DMC_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct AliasTable {
+    int bits = 0;
+    std::vector<uint64_t> mass;    // integer masses, sum 2^32
+    std::vector<uint32_t> thresh;  // canonical thresholds (a full column holds 2^(32-bits))
+    std::vector<uint32_t> alias;
+    std::vector<uint32_t> packed;  // device form (pack_alias)
+};
+
+bool build_alias(const std::vector<double> &w, AliasTable &t, std::string &why);
+
+// A job of a launch: the caller's description plus its normalisation and its
+// device descriptor (offsets relative to the launch's tally base).
+struct JobHost {
+    dmc_job job{};
+    std::vector<double> times;
+    dmc_geometry_desc geom{};
+    double power = 0.0;       // steady: source power per unit area (slab, film) or length (cell); transient: energy
+    double avg_volume = 1.0;  // mu(R) of the conductivity average
+    int64_t size = 0;         // doubles of its tally block
+    JobDev dev{};
+};
+
+dmc_status prepare_job(const dmc_job &jb, JobHost &h);
+dmc_status run_opts_check(const dmc_run_opts &o);
+
+// Device regions a launch uses besides the material tables.
+struct LaunchBuffers {
+    JobDev *jobs = nullptr;           // n_jobs descriptors
+    double *times = nullptr;          // concatenated snapshot times
+    double *tally = nullptr;          // tally base (job offsets are relative to it)
+    unsigned long long *stats = nullptr;  // n_jobs * kStats counters
+    unsigned long long *queue = nullptr;  // 2 words
+};
+
+// Plans LDS privatisation and occupancy, uploads the descriptors, clears the
+// counters (and the tallies if zero_tally), records ev0, enqueues the
+// trajectory launch(es) and records ev1, all on `stream`.  `devs` receives the
+// LDS offsets chosen.
+dmc_status enqueue_launch(const struct ::dmc_material *M, std::vector<JobDev> &devs, const std::vector<double> &times,
+                          const LaunchBuffers &b, size_t tally_doubles, bool zero_tally, const dmc_run_opts &o,
+                          hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+
+}  // namespace dmc
+
+struct dmc_material {
+    int32_t K = 0;
+    double T_eq = 0.0;
+    std::vector<double> v, tau, C;
+    double C_tot = 0.0, G_tau = 0.0, G_v = 0.0;
+    dmc::AliasTable gain, init, flux;
+    uint32_t *d_gain = nullptr, *d_init = nullptr, *d_flux = nullptr;
+    float4 *d_st32 = nullptr;
+    double2 *d_st64 = nullptr;
+    int device = 0;
+    ~dmc_material();
+};
+
+struct dmc_geometry {
+    dmc_geometry_desc d;
+};
+
+struct dmc_result {
+    const dmc_material *mat = nullptr;
+    std::vector<dmc::JobHost> jobs;
+    void *dev_mem = nullptr;          // device allocation owned by this result (hipFree on destroy)
+    std::function<void()> on_destroy; // releases memory owned elsewhere (server arena)
+    double *d_tally = nullptr;
+    unsigned long long *d_stats = nullptr;
+    size_t tally_doubles = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool synced = false;
+    std::vector<double> h_tally;
+    std::vector<unsigned long long> h_stats;
+    double kernel_ms = 0.0;
+    ~dmc_result();
+};

@@ -1,0 +1,97 @@
+// Internal layout shared by the library's host code and its HIP kernels.
+// Nothing here is part of the public C ABI (include/dmc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dmc {
+
+constexpr uint32_t kIterCap = 1u << 24;  // safety cap on flights per particle
+constexpr int kPosAttempts = 64;         // rejection attempts for positions in a pore cell
+constexpr int kMaxJobs = 4096;
+constexpr int kMaxBins = 4096;
+constexpr int kMaxTimes = 1024;
+constexpr int kMaxHj = 1024;
+constexpr int kLdsStatJobs = 64;         // per-job counters privatised in LDS up to this many jobs
+constexpr int kStats = 5;                // particles, scatters, boundary, iterations, capped
+
+enum Geom : int32_t { GEOM_SLAB = 0, GEOM_FILM = 1, GEOM_PORE = 2, GEOM_HALF = 3, GEOM_ANY = 9 };
+enum Wall : int32_t { WALL_ISOTHERMAL = 0, WALL_ADIABATIC = 1, WALL_PERIODIC = 2 };
+enum Src : int32_t { SRC_WALLS = 0, SRC_GAUSSIAN = 1, SRC_GRADIENT = 2 };
+enum Form : int32_t { FORM_PLAIN = 0, FORM_PERSISTENT = 1 };
+enum Tag : uint32_t { TAG_STEP = 0, TAG_EMIT_A = 1, TAG_EMIT_B = 2 };
+constexpr int32_t kNoSurface = -1;
+
+// One simulation inside a launch.  Particle pid of the job has queue index base + pid.
+struct alignas(16) JobDev {
+    uint64_t base, n;       // queue range [base, base + n) of this launch
+    uint64_t pid0;          // pid of the range's first particle (a slice of a longer job)
+    uint32_t key0, key1;
+    int32_t geom, src;
+    double length, radius;
+    int32_t wall_type[2];
+    uint64_t spec_thr[2];   // specular iff the word is below this (p = 1 gives 2^32)
+    int32_t n_src;          // wall sources (1 or 2)
+    int32_t src_wall[2];
+    uint32_t src_packed[2]; // alias table of the two wall-source powers (1 index bit)
+    double wall_sign[2];    // sign of particles emitted by each wall
+    double sign0;           // gaussian: sign(dT); gradient: -sign(dT/dz)
+    double sigma;           // gaussian: radius / sqrt(2)
+    // tallies: offsets are in doubles from the launch's tally base / the LDS tally base
+    int32_t n_bins, n_batches;
+    double bins_per_len, bin_width;
+    int64_t off_bins, off_kappa, off_hj, off_snap, off_snap_abs;
+    int32_t lds_bins, lds_kappa, lds_hj;  // -1: accumulate in global memory
+    int32_t kmax, n_hj;
+    int32_t n_times, times_off;
+    int32_t grid[3], pad0;
+    double grid_lo[3], grid_ext[3];  // lower bound and extent hi - lo
+    int64_t ncell;
+};
+
+struct KArgs {
+    const JobDev *jobs;
+    int32_t n_jobs;
+    int32_t K;
+    uint64_t qbegin;                // plain form: first queue index of this launch
+    uint64_t total;                 // one past the last queue index of this launch
+    unsigned long long *queue;      // next queue index (persistent form)
+    int32_t gain_bits, flux_bits, init_bits, pad0;
+    const uint32_t *gain_packed, *flux_packed, *init_packed;
+    const float4 *st32;             // per state: v, tau, 1/tau, 0
+    const double2 *st64;            // per state: v, tau
+    double *tally;
+    const double *times;
+    uint32_t *nscat_out;            // optional, indexed by queue index
+    unsigned long long *stats;      // [n_jobs][kStats]
+    int32_t chunk, refill_min;
+    int32_t lds_tally_doubles;      // LDS tally size; 0 = none
+    int32_t lds_stats;              // 1: per-job counters in LDS
+    int32_t kpad;                   // 2^gain_bits
+};
+
+// Packed alias entry: column idx of a table with b index bits keeps idx iff
+// the low (32 - b) bits of the word are below the entry's low bits, else it
+// takes the entry's high b bits as the state.  Full columns are stored as
+// threshold U - 1 with alias = self, which draws identically to threshold U.
+inline uint32_t pack_alias(uint32_t thresh, uint32_t alias, uint32_t idx, int bits)
+{
+    const uint64_t U = 1ull << (32 - bits);
+    uint32_t t = thresh, a = alias;
+    if ((uint64_t)thresh >= U) { t = (uint32_t)(U - 1); a = idx; }
+    return (uint32_t)(((uint64_t)a << (32 - bits)) | t);
+}
+
+// Launch entry points (dmc_kernels.hip).
+hipError_t launch_trajectories(const KArgs &a, int precision, int form, bool slab_only, int block, int grid,
+                               size_t lds_bytes, hipStream_t stream);
+hipError_t launch_fill(double *p, size_t n_doubles, unsigned long long *q, size_t n_u64, hipStream_t stream);
+hipError_t launch_debug_philox(uint64_t seed, const uint64_t *pid, const uint32_t *k, const uint32_t *tag,
+                               uint32_t *out, size_t n, hipStream_t stream);
+hipError_t launch_debug_alias(const uint32_t *packed, int bits, const uint32_t *words, uint32_t *states, size_t n,
+                              hipStream_t stream);
+int max_lds_bytes();
+int occupancy_blocks(int precision, int form, bool slab_only, int block, size_t lds_bytes);
+
+}  // namespace dmc

@@ -1,0 +1,920 @@
+// dmc_kernels.hip -- trajectory kernels for gfx950 (CDNA4).
+//
+// One wavefront lane carries one deviational particle through steps I-VI of
+// the particle algorithm (draw from the source term, exponential free flight
+// with mean tau, boundary search, boundary interaction or scattering from the
+// normalised gain distribution of Eq. (2), segment scoring with the
+// track-length estimator of Eq. (4) or the snapshot estimator of Eq. (3)).
+// Particles never interact, so lanes never communicate except to take work
+// from the particle queue and to combine tallies.
+//
+// Compile-time policies of the single kernel template:
+//   R      float  : flight, intersection and sampling in FP32 (tallies FP64)
+//          double : every step in FP64 (parity mode; arithmetic in the same
+//                   order as the FP64 reference so that realisations agree)
+//   FORM   PLAIN      one thread per particle run to completion; tables read
+//                     from global memory; every contribution a direct FP64
+//                     global atomic
+//          PERSISTENT waves take chunks of particle indices from a queue and
+//                     refill free lanes; gain table and state data staged in
+//                     LDS; per-lane bin caches flushed to LDS-privatised
+//                     tallies that are added to HBM once per workgroup
+//   G      GEOM_SLAB  cross-plane slab only (dead components eliminated)
+//          GEOM_ANY   every geometry and source, chosen per lane
+//
+// Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = seed and
+// counter = (pid lo, pid hi, k, tag); one block per flight k (tag STEP), one
+// or more blocks at emission (tags EMIT_A, EMIT_B).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "dmc_internal.h"
+
+namespace dmc {
+namespace {
+
+constexpr double kTwoPi = 2.0 * 3.14159265358979323846;
+
+// ---------------------------------------------------------------- Philox ----
+
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint32_t alias_draw(const uint32_t *tab, int bits, uint32_t w)
+{
+    const uint32_t idx = w >> (32 - bits);
+    const uint32_t mask = (1u << (32 - bits)) - 1u;
+    const uint32_t e = tab[idx];
+    return ((w & mask) < (e & mask)) ? idx : (e >> (32 - bits));
+}
+
+// ------------------------------------------------------ precision traits ----
+
+template <typename R>
+struct Pr;
+
+template <>
+struct Pr<double> {
+    static constexpr double inf() { return __builtin_huge_val(); }
+    __device__ static double u(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
+    __device__ static double flight(double tau, uint32_t w) { return -tau * log(u(w)); }
+    __device__ static double sq(double x) { return sqrt(x); }
+    __device__ static void cs(uint32_t w, double &c, double &s)
+    {
+        const double ph = kTwoPi * u(w);
+        c = cos(ph);
+        s = sin(ph);
+    }
+    __device__ static double div(double a, double b) { return a / b; }
+    __device__ static double ptime(double t, double tau, double) { return t / tau; }
+    __device__ static double lg(double x) { return log(x); }
+    // FP64 keeps the reference's arithmetic unchanged
+    __device__ static double nonneg(double t) { return t; }
+};
+
+template <>
+struct Pr<float> {
+    static constexpr float inf() { return __builtin_huge_valf(); }
+    // ((w >> 8) + 1/2) 2^-24: exact, strictly inside (0, 1)
+    __device__ static float u(uint32_t w) { return ((float)(w >> 8) + 0.5f) * 5.9604644775390625e-08f; }
+    __device__ static float flight(float tau, uint32_t w) { return -tau * __logf(u(w)); }
+    __device__ static float sq(float x) { return __builtin_amdgcn_sqrtf(x); }
+    // v_sin / v_cos take revolutions: sin(2 pi u) = sin_rev(u)
+    __device__ static void cs(uint32_t w, float &c, float &s)
+    {
+        const float r = u(w);
+        c = __builtin_amdgcn_cosf(r);
+        s = __builtin_amdgcn_sinf(r);
+    }
+    __device__ static float div(float a, float b) { return __fdividef(a, b); }
+    __device__ static float ptime(float t, float, float itau) { return t * itau; }
+    __device__ static float lg(float x) { return __logf(x); }
+    // a position rounded just past a wall must not yield a negative flight time
+    __device__ static float nonneg(float t) { return fmaxf(t, 0.0f); }
+};
+
+// ------------------------------------------------------------ lane state ----
+
+template <typename R>
+struct Lane {
+    R x, y, z, ox, oy, oz;  // position and unit direction
+    R v, tau, itau;         // group speed, relaxation time, 1/tau of the current state
+    R s;                    // sign
+    int32_t last;           // surface the particle rests on (excluded from the next search)
+    uint32_t k, nscat, nbound;
+    uint64_t pid, qidx;
+    int32_t job, batch;
+    // cached job parameters
+    int32_t geom, src, n_bins, n_hj, kmax, n_times;
+    R len, bpl, bw;
+    uint32_t key0, key1;
+    // accumulators
+    double t, Lz, h;
+    int32_t cbin;
+    double c0, c1, c2;
+    int32_t tcur;
+};
+
+struct Shared {
+    uint32_t *gain;              // packed gain table: LDS (persistent) or global (plain)
+    const void *st;              // per-state data: LDS (persistent) or global (plain)
+    double *ltally;              // LDS tallies (slots used only where a job's lds offset >= 0)
+    unsigned long long *lstats;  // LDS per-job counters (used only if KArgs::lds_stats)
+};
+
+template <typename R>
+__device__ __forceinline__ void load_state(Lane<R> &p, const KArgs &a, const Shared &sh, uint32_t m);
+
+template <>
+__device__ __forceinline__ void load_state<float>(Lane<float> &p, const KArgs &a, const Shared &sh, uint32_t m)
+{
+    const float4 q = reinterpret_cast<const float4 *>(sh.st)[m];
+    p.v = q.x;
+    p.tau = q.y;
+    p.itau = q.z;
+}
+
+template <>
+__device__ __forceinline__ void load_state<double>(Lane<double> &p, const KArgs &a, const Shared &sh, uint32_t m)
+{
+    const double2 q = reinterpret_cast<const double2 *>(sh.st)[m];
+    p.v = q.x;
+    p.tau = q.y;
+    p.itau = 0.0;
+}
+
+// ------------------------------------------------------- tally helpers ----
+
+__device__ __forceinline__ void gadd(double *p, double v) { atomicAdd(p, v); }
+__device__ __forceinline__ void gaddu(unsigned long long *p, unsigned long long v) { atomicAdd(p, v); }
+
+// Adds to a tally slot that lives in LDS when lds_off >= 0, else in HBM.
+__device__ __forceinline__ void tadd(const KArgs &a, const Shared &sh, int32_t lds_off, int64_t g_off, int64_t idx,
+                                     double v)
+{
+    if (lds_off >= 0)
+        atomicAdd(sh.ltally + lds_off + idx, v);
+    else
+        gadd(a.tally + g_off + idx, v);
+}
+
+// ------------------------------------------------------------ emission ----
+
+// Lambertian direction about the inward normal sgn * e_axis (axis 0 or 2):
+// mu = sqrt(u); tangent frame (x, y) for a z normal and (y, z) for an x normal.
+template <typename R>
+__device__ __forceinline__ void lambertian_plane(Lane<R> &p, int axis, R sgn, uint32_t w2, uint32_t w3)
+{
+    const R mu = Pr<R>::sq(Pr<R>::u(w2));
+    R c, s;
+    Pr<R>::cs(w3, c, s);
+    const R st = Pr<R>::sq((R)1 - mu * mu);
+    if (axis == 2) {
+        p.ox = st * c;
+        p.oy = st * s;
+        p.oz = mu * sgn;
+    } else {
+        p.ox = mu * sgn;
+        p.oy = st * c;
+        p.oz = st * s;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void isotropic(Lane<R> &p, uint32_t w2, uint32_t w3)
+{
+    const R mu = (R)2 * Pr<R>::u(w2) - (R)1;
+    R c, s;
+    Pr<R>::cs(w3, c, s);
+    const R st = Pr<R>::sq((R)1 - mu * mu);
+    p.ox = st * c;
+    p.oy = st * s;
+    p.oz = mu;
+}
+
+template <typename R, int G>
+__device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, uint64_t qidx, int job)
+{
+    const uint64_t pid = J.pid0 + (qidx - J.base);
+    p.pid = pid;
+    p.qidx = qidx;
+    p.job = job;
+    p.batch = (int32_t)(pid % (uint64_t)J.n_batches);
+    p.geom = (G == GEOM_ANY) ? J.geom : G;
+    p.src = J.src;
+    p.n_bins = J.n_bins;
+    p.n_hj = J.n_hj;
+    p.kmax = J.kmax;
+    p.n_times = J.n_times;
+    p.len = (R)J.length;
+    p.bpl = (R)J.bins_per_len;
+    p.bw = (R)J.bin_width;
+    p.key0 = J.key0;
+    p.key1 = J.key1;
+    p.x = p.y = p.z = (R)0;
+    p.last = kNoSurface;
+    p.k = 0;
+    p.nscat = 0;
+    p.nbound = 0;
+    p.t = 0.0;
+    p.Lz = 0.0;
+    p.h = 0.0;
+    p.cbin = -1;
+    p.c0 = p.c1 = p.c2 = 0.0;
+    p.tcur = 0;
+
+    const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
+    const uint4 A = philox(plo, phi, 0u, TAG_EMIT_A, p.key0, p.key1);
+    uint32_t m;
+    const int src = (G == GEOM_SLAB) ? (int)SRC_WALLS : p.src;
+    if (src == SRC_WALLS) {
+        const uint32_t j = (J.n_src > 1) ? alias_draw(J.src_packed, 1, A.x) : 0u;
+        const int wall = J.src_wall[j];
+        m = alias_draw(a.flux_packed, a.flux_bits, A.y);
+        const int axis = (p.geom == GEOM_FILM) ? 0 : 2;
+        lambertian_plane(p, axis, wall == 0 ? (R)1 : (R)-1, A.z, A.w);
+        const R c = (wall == 0) ? (R)0 : p.len;
+        if (axis == 2)
+            p.z = c;
+        else
+            p.x = c;
+        p.last = wall;
+        p.s = (R)J.wall_sign[wall];
+    } else if (src == SRC_GAUSSIAN) {
+        const uint4 B = philox(plo, phi, 0u, TAG_EMIT_B, p.key0, p.key1);
+        m = alias_draw(a.init_packed, a.init_bits, A.y);
+        isotropic(p, A.z, A.w);
+        const R sigma = (R)J.sigma;
+        const R rho = Pr<R>::sq((R)-2 * Pr<R>::lg(Pr<R>::u(B.x)));
+        R c, s;
+        Pr<R>::cs(B.y, c, s);
+        p.x = sigma * rho * c;
+        p.y = sigma * rho * s;
+        const R rz = Pr<R>::sq((R)-2 * Pr<R>::lg(Pr<R>::u(B.z)));
+        R c2, s2;
+        Pr<R>::cs(B.w, c2, s2);
+        p.z = fabs(sigma * rz * c2);
+        p.s = (R)J.sign0;
+    } else {  // gradient source, Eq. (6)
+        const uint4 B = philox(plo, phi, 0u, TAG_EMIT_B, p.key0, p.key1);
+        m = alias_draw(a.flux_packed, a.flux_bits, A.y);
+        const R sz = (B.w >> 31) ? (R)-1 : (R)1;
+        lambertian_plane(p, 2, sz, A.z, A.w);
+        p.s = sz * (R)J.sign0;
+        if (p.geom == GEOM_FILM) {
+            p.x = p.len * Pr<R>::u(B.x);
+        } else {
+            const R c = (R)0.5 * p.len;
+            const R r2 = (R)J.radius * (R)J.radius;
+            bool ok = false;
+            for (uint32_t att = 0; att < (uint32_t)kPosAttempts && !ok; ++att) {
+                const uint4 Bb = (att == 0) ? B : philox(plo, phi, att, TAG_EMIT_B, p.key0, p.key1);
+                const R x = p.len * Pr<R>::u(Bb.x), z = p.len * Pr<R>::u(Bb.y);
+                if ((x - c) * (x - c) + (z - c) * (z - c) > r2) {
+                    p.x = x;
+                    p.z = z;
+                    ok = true;
+                }
+            }
+            if (!ok) {
+                p.x = (R)0;
+                p.z = (R)0;
+            }
+        }
+    }
+    load_state(p, a, sh, m);
+}
+
+// ------------------------------------------------------------- scoring ----
+
+template <typename R, int FORM>
+__device__ __forceinline__ void bin_flush(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J)
+{
+    if (p.cbin < 0) return;
+    const int64_t base = ((int64_t)p.batch * 3) * p.n_bins + p.cbin;
+    tadd(a, sh, J.lds_bins, J.off_bins, base, p.c0);
+    tadd(a, sh, J.lds_bins, J.off_bins, base + p.n_bins, p.c1);
+    tadd(a, sh, J.lds_bins, J.off_bins, base + 2 * p.n_bins, p.c2);
+    p.cbin = -1;
+    p.c0 = p.c1 = p.c2 = 0.0;
+}
+
+// Time t spent in bin k: TIME += s t, PTIME += s t / tau, DISP += s v Omega_z t.
+template <typename R, int FORM>
+__device__ __forceinline__ void bin_add(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, int k, R t,
+                                        R vz, bool cache)
+{
+    const double d0 = (double)(p.s * t);
+    const double d1 = (double)(p.s * Pr<R>::ptime(t, p.tau, p.itau));
+    const double d2 = (double)(p.s * vz * t);
+    if (FORM == FORM_PERSISTENT && cache) {
+        if (k != p.cbin) {
+            bin_flush<R, FORM>(p, a, sh, J);
+            p.cbin = k;
+        }
+        p.c0 += d0;
+        p.c1 += d1;
+        p.c2 += d2;
+    } else {
+        const int64_t base = ((int64_t)p.batch * 3) * p.n_bins + k;
+        tadd(a, sh, J.lds_bins, J.off_bins, base, d0);
+        tadd(a, sh, J.lds_bins, J.off_bins, base + p.n_bins, d1);
+        tadd(a, sh, J.lds_bins, J.off_bins, base + 2 * p.n_bins, d2);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ int bin_of(R c, R bpl, int nb)
+{
+    int k = (int)floor(c * bpl);
+    return k < 0 ? 0 : (k > nb - 1 ? nb - 1 : k);
+}
+
+// Track-length scoring of one segment into the 1-D bins (slab: z, film: x).
+template <typename R, int FORM>
+__device__ void score_bins(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, R seg)
+{
+    const bool zax = (p.geom != GEOM_FILM);
+    const R ca = zax ? p.z : p.x;
+    const R wa = p.v * (zax ? p.oz : p.ox);
+    const R vz = p.v * p.oz;
+    const int nb = p.n_bins;
+    const int ka = bin_of(ca, p.bpl, nb);
+    if (wa == (R)0) {
+        bin_add<R, FORM>(p, a, sh, J, ka, seg, vz, true);
+        return;
+    }
+    const R cb = ca + wa * seg;
+    const int kb = bin_of(cb, p.bpl, nb);
+    if (ka == kb) {
+        bin_add<R, FORM>(p, a, sh, J, ka, seg, vz, true);
+        return;
+    }
+    const R aw = fabs(wa);
+    const R inv = (R)1 / aw;
+    const R bw = p.bw;
+    if (wa > (R)0) {
+        const R t0 = fmax(((R)(ka + 1) * bw - ca) * inv, (R)0);
+        bin_add<R, FORM>(p, a, sh, J, ka, t0, vz, true);
+        const R tin = bw * inv;
+        for (int k = ka + 1; k < kb; ++k) bin_add<R, FORM>(p, a, sh, J, k, tin, vz, false);
+        const R t1 = fmax((cb - (R)kb * bw) * inv, (R)0);
+        bin_add<R, FORM>(p, a, sh, J, kb, t1, vz, true);
+    } else {
+        const R t0 = fmax((ca - (R)ka * bw) * inv, (R)0);
+        bin_add<R, FORM>(p, a, sh, J, ka, t0, vz, true);
+        const R tin = bw * inv;
+        for (int k = ka - 1; k > kb; --k) bin_add<R, FORM>(p, a, sh, J, k, tin, vz, false);
+        const R t1 = fmax(((R)(kb + 1) * bw - cb) * inv, (R)0);
+        bin_add<R, FORM>(p, a, sh, J, kb, t1, vz, true);
+    }
+}
+
+// Snapshot estimator (Eq. (3)) at every sample time in [t, t + seg).
+template <typename R>
+__device__ void score_snapshots(Lane<R> &p, const KArgs &a, const JobDev &J, double seg)
+{
+    const double ta = p.t, tb = p.t + seg;
+    const double *times = a.times + J.times_off;
+    while (p.tcur < p.n_times && times[p.tcur] < tb) {
+        const double tj = times[p.tcur];
+        if (tj >= ta) {
+            const double dt = tj - ta;
+            const double pos[3] = {(double)p.x + (double)(p.v * p.ox) * dt, (double)p.y + (double)(p.v * p.oy) * dt,
+                                   (double)p.z + (double)(p.v * p.oz) * dt};
+            int64_t idx[3];
+            bool inside = true;
+            for (int d = 0; d < 3; ++d) {
+                const double f = (pos[d] - J.grid_lo[d]) / J.grid_ext[d] * (double)J.grid[d];
+                const double fl = floor(f);
+                if (!(fl >= 0.0 && fl < (double)J.grid[d])) {
+                    inside = false;
+                    break;
+                }
+                idx[d] = (int64_t)fl;
+            }
+            const int64_t cell = inside ? (idx[2] * J.grid[1] + idx[1]) * J.grid[0] + idx[0] : J.ncell;
+            const int64_t o = (int64_t)p.tcur * (J.ncell + 1) + cell;
+            gadd(a.tally + J.off_snap + o, (double)p.s);
+            gadd(a.tally + J.off_snap_abs + o, 1.0);
+        }
+        ++p.tcur;
+    }
+}
+
+// ------------------------------------------------------ boundary search ----
+
+// Earliest surface hit time along x + v Omega t, excluding p.last.
+template <typename R>
+__device__ __forceinline__ R search(const Lane<R> &p, const JobDev &J, int geom, int32_t &surf)
+{
+    R best = Pr<R>::inf();
+    surf = kNoSurface;
+    if (geom == GEOM_SLAB || geom == GEOM_FILM) {
+        const R c = (geom == GEOM_SLAB) ? p.z : p.x;
+        const R w = p.v * ((geom == GEOM_SLAB) ? p.oz : p.ox);
+        if (w > (R)0 && p.last != 1) {
+            best = Pr<R>::div(p.len - c, w);
+            surf = 1;
+        } else if (w < (R)0 && p.last != 0) {
+            best = Pr<R>::div((R)0 - c, w);
+            surf = 0;
+        }
+    } else if (geom == GEOM_HALF) {
+        const R w = p.v * p.oz;
+        if (w < (R)0 && p.last != 0) {
+            best = Pr<R>::div((R)0 - p.z, w);
+            surf = 0;
+        }
+    } else {  // pore cell: faces 0: x=0, 1: x=P, 2: z=0, 3: z=P, 4: pore surface
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            const R c = (f == 0) ? p.x : p.z;
+            const R w = p.v * ((f == 0) ? p.ox : p.oz);
+            R t = Pr<R>::inf();
+            int32_t id = kNoSurface;
+            if (w > (R)0 && p.last != 2 * f + 1) {
+                t = Pr<R>::div(p.len - c, w);
+                id = 2 * f + 1;
+            } else if (w < (R)0 && p.last != 2 * f) {
+                t = Pr<R>::div((R)0 - c, w);
+                id = 2 * f;
+            }
+            if (t < best) {
+                best = t;
+                surf = id;
+            }
+        }
+        const R rad = (R)J.radius;
+        if (rad > (R)0 && p.last != 4) {
+            const R c = (R)0.5 * p.len;
+            const R dx = p.x - c, dz = p.z - c;
+            const R aq = p.ox * p.ox + p.oz * p.oz;
+            const R bq = dx * p.ox + dz * p.oz;
+            const R cq = dx * dx + dz * dz - rad * rad;
+            if (aq > (R)0 && bq < (R)0) {
+                R dist = Pr<R>::inf();
+                if (cq <= (R)0)
+                    dist = (R)0;
+                else {
+                    const R disc = bq * bq - aq * cq;
+                    if (disc > (R)0) dist = Pr<R>::div(-bq - Pr<R>::sq(disc), aq);
+                }
+                const R t = Pr<R>::div(dist, p.v);
+                if (t < best) {
+                    best = t;
+                    surf = 4;
+                }
+            }
+        }
+    }
+    return Pr<R>::nonneg(best);
+}
+
+// Step IVa.  Returns true if the particle is absorbed.
+template <typename R>
+__device__ bool interact(Lane<R> &p, const JobDev &J, int32_t surf, const uint4 &w)
+{
+    if (p.geom == GEOM_PORE) {
+        if (surf < 4) {
+            const bool xf = surf < 2;
+            const R v = (surf % 2 == 1) ? (R)0 : p.len;
+            if (xf)
+                p.x = v;
+            else
+                p.z = v;
+            p.last = (surf % 2 == 1) ? surf - 1 : surf + 1;
+            return false;
+        }
+        const R c = (R)0.5 * p.len;
+        const R nx = p.x - c, nz = p.z - c;
+        const R nn = Pr<R>::sq(nx * nx + nz * nz);
+        const R n0 = nx / nn, n2 = nz / nn;
+        if ((uint64_t)w.y < J.spec_thr[0]) {
+            const R dn = p.ox * n0 + p.oz * n2;
+            p.ox = p.ox - (R)2 * dn * n0;
+            p.oz = p.oz - (R)2 * dn * n2;
+        } else {
+            const R mu = Pr<R>::sq(Pr<R>::u(w.z));
+            R c3, s3;
+            Pr<R>::cs(w.w, c3, s3);
+            const R st = Pr<R>::sq((R)1 - mu * mu);
+            p.ox = mu * n0 + st * (s3 * -n2);
+            p.oy = st * c3;
+            p.oz = mu * n2 + st * (s3 * n0);
+        }
+        p.last = 4;
+        return false;
+    }
+    const int wall = (p.geom == GEOM_HALF) ? 0 : surf;
+    const int ax = (p.geom == GEOM_FILM) ? 0 : 2;
+    const int32_t type = J.wall_type[wall];
+    if (type == WALL_ISOTHERMAL) return true;
+    if (type == WALL_PERIODIC) {
+        const R v = (wall == 1) ? (R)0 : p.len;
+        if (ax == 2)
+            p.z = v;
+        else
+            p.x = v;
+        p.last = (wall == 1) ? 0 : 1;
+        return false;
+    }
+    if ((uint64_t)w.y < J.spec_thr[wall]) {
+        if (ax == 2)
+            p.oz = -p.oz;
+        else
+            p.ox = -p.ox;
+    } else {
+        lambertian_plane(p, ax, wall == 0 ? (R)1 : (R)-1, w.z, w.w);
+    }
+    p.last = wall;
+    return false;
+}
+
+// ---------------------------------------------------------------- finish ----
+
+template <typename R, int FORM>
+__device__ void finish(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, bool capped)
+{
+    if (p.n_bins > 0) bin_flush<R, FORM>(p, a, sh, J);
+    if (J.off_kappa >= 0) {
+        tadd(a, sh, J.lds_kappa, J.off_kappa, 0, p.Lz);
+        tadd(a, sh, J.lds_kappa, J.off_kappa, 1, p.Lz * p.Lz);
+    }
+    if (p.n_hj > 0 && p.nscat < (uint32_t)p.n_hj) {
+        tadd(a, sh, J.lds_hj, J.off_hj, p.nscat, p.h);
+        tadd(a, sh, J.lds_hj, J.off_hj, p.n_hj + p.nscat, p.h * p.h);
+    }
+    if (a.nscat_out) a.nscat_out[p.qidx] = p.nscat;
+    const unsigned long long vals[kStats] = {1ull, p.nscat, p.nbound, p.k, capped ? 1ull : 0ull};
+    if (a.lds_stats) {
+#pragma unroll
+        for (int i = 0; i < kStats; ++i)
+            if (vals[i]) atomicAdd(sh.lstats + p.job * kStats + i, vals[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kStats; ++i)
+            if (vals[i]) gaddu(a.stats + (int64_t)p.job * kStats + i, vals[i]);
+    }
+}
+
+// ------------------------------------------------------------------ step ----
+
+// One iteration of steps II-VI.  Returns 0 if the particle goes on, 1 if it
+// ended, 2 if it hit the flight cap.
+template <typename R, int FORM, int G>
+__device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J)
+{
+    const uint4 w = philox((uint32_t)p.pid, (uint32_t)(p.pid >> 32), p.k, TAG_STEP, p.key0, p.key1);
+    ++p.k;
+    const R dt = Pr<R>::flight(p.tau, w.x);                           // step II
+    int32_t surf;
+    const int geom = (G == GEOM_ANY) ? p.geom : G;
+    const R tb = search(p, J, geom, surf);                           // step III
+    const bool boundary = (tb <= dt);
+    const R seg = boundary ? tb : dt;
+    // step V: sample the segment
+    if (p.n_bins > 0) score_bins<R, FORM>(p, a, sh, J, seg);
+    const bool gradient = (G == GEOM_ANY) && (p.src == SRC_GRADIENT);
+    if (gradient) {
+        const double dz = (double)(p.s * p.v * p.oz * seg);
+        p.Lz += dz;
+        if (p.nscat < (uint32_t)p.n_hj) p.h += dz;
+    }
+    if (G == GEOM_ANY && p.n_times > 0) {
+        score_snapshots(p, a, J, (double)seg);
+        if (p.t + (double)seg > a.times[J.times_off + p.n_times - 1]) return 1;  // step VI
+    }
+    // move
+    p.x += p.v * p.ox * seg;
+    p.y += p.v * p.oy * seg;
+    p.z += p.v * p.oz * seg;
+    p.t += (double)seg;
+    if (boundary) {                                                   // step IVa
+        if (geom == GEOM_SLAB || geom == GEOM_HALF)
+            p.z = (surf == 1) ? p.len : (R)0;
+        else if (geom == GEOM_FILM)
+            p.x = (surf == 1) ? p.len : (R)0;
+        else if (surf < 4) {
+            const R v = (surf % 2 == 1) ? p.len : (R)0;
+            if (surf < 2)
+                p.x = v;
+            else
+                p.z = v;
+        }
+        ++p.nbound;
+        if (interact(p, J, surf, w)) return 1;
+    } else {                                                          // step IVb
+        const uint32_t m = alias_draw(sh.gain, a.gain_bits, w.y);
+        load_state(p, a, sh, m);
+        isotropic(p, w.z, w.w);
+        p.last = kNoSurface;
+        if (gradient && p.nscat < (uint32_t)p.n_hj) {
+            tadd(a, sh, J.lds_hj, J.off_hj, p.nscat, p.h);
+            tadd(a, sh, J.lds_hj, J.off_hj, p.n_hj + p.nscat, p.h * p.h);
+            p.h = 0.0;
+        }
+        ++p.nscat;
+        if (p.kmax >= 0 && p.nscat >= (uint32_t)p.kmax) return 1;
+    }
+    if (p.k >= kIterCap) return 2;
+    return 0;
+}
+
+__device__ __forceinline__ int find_job(const KArgs &a, uint64_t q, int hint)
+{
+    int j = hint;
+    while (j + 1 < a.n_jobs && q >= a.jobs[j + 1].base) ++j;
+    return j;
+}
+
+// ------------------------------------------------------------ LDS setup ----
+
+// LDS layout (persistent form): packed gain table (2^bits u32, padded to 16
+// bytes), per-state data (16 bytes each), privatised tallies (doubles), per-job
+// counters.  The plain form keeps the tables in global memory and only the
+// counters in LDS.  Pointers into LDS are always derived from the shared
+// array so the compiler emits LDS instructions for them.
+template <typename R, int FORM>
+__device__ Shared setup_shared(const KArgs &a, unsigned char *smem)
+{
+    Shared sh;
+    size_t off = 0;
+    if (FORM == FORM_PERSISTENT) {
+        uint32_t *g = reinterpret_cast<uint32_t *>(smem);
+        for (int i = threadIdx.x; i < a.kpad; i += blockDim.x) g[i] = a.gain_packed[i];
+        off = ((size_t)a.kpad * 4 + 15) & ~(size_t)15;
+        if (sizeof(R) == 4) {
+            float4 *st = reinterpret_cast<float4 *>(smem + off);
+            for (int i = threadIdx.x; i < a.K; i += blockDim.x) st[i] = a.st32[i];
+            sh.st = st;
+        } else {
+            double2 *st = reinterpret_cast<double2 *>(smem + off);
+            for (int i = threadIdx.x; i < a.K; i += blockDim.x) st[i] = a.st64[i];
+            sh.st = st;
+        }
+        off += (size_t)a.K * 16;
+        sh.gain = g;
+        off = (off + 15) & ~(size_t)15;
+        sh.ltally = reinterpret_cast<double *>(smem + off);
+        for (int i = threadIdx.x; i < a.lds_tally_doubles; i += blockDim.x) sh.ltally[i] = 0.0;
+        off += (size_t)a.lds_tally_doubles * 8;
+    } else {
+        sh.gain = const_cast<uint32_t *>(a.gain_packed);
+        sh.st = (sizeof(R) == 4) ? (const void *)a.st32 : (const void *)a.st64;
+        sh.ltally = reinterpret_cast<double *>(smem);
+    }
+    sh.lstats = reinterpret_cast<unsigned long long *>(smem + off);
+    if (a.lds_stats)
+        for (int i = threadIdx.x; i < a.n_jobs * kStats; i += blockDim.x) sh.lstats[i] = 0ull;
+    __syncthreads();
+    return sh;
+}
+
+// Adds the workgroup's LDS tallies and counters to HBM.
+__device__ void flush_shared(const KArgs &a, const Shared &sh)
+{
+    __syncthreads();
+    if (a.lds_tally_doubles > 0) {
+        for (int j = 0; j < a.n_jobs; ++j) {
+            const JobDev &J = a.jobs[j];
+            if (J.lds_bins >= 0) {
+                const int n = J.n_batches * 3 * J.n_bins;
+                for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                    const double v = sh.ltally[J.lds_bins + i];
+                    if (v != 0.0) gadd(a.tally + J.off_bins + i, v);
+                }
+            }
+            if (J.lds_kappa >= 0 && threadIdx.x < 2) {
+                const double v = sh.ltally[J.lds_kappa + threadIdx.x];
+                if (v != 0.0) gadd(a.tally + J.off_kappa + threadIdx.x, v);
+            }
+            if (J.lds_hj >= 0) {
+                for (int i = threadIdx.x; i < 2 * J.n_hj; i += blockDim.x) {
+                    const double v = sh.ltally[J.lds_hj + i];
+                    if (v != 0.0) gadd(a.tally + J.off_hj + i, v);
+                }
+            }
+        }
+    }
+    if (a.lds_stats) {
+        for (int i = threadIdx.x; i < a.n_jobs * kStats; i += blockDim.x) {
+            const unsigned long long v = sh.lstats[i];
+            if (v) gaddu(a.stats + i, v);
+        }
+    }
+}
+
+// --------------------------------------------------------------- kernels ----
+
+template <typename R, int G>
+__global__ void __launch_bounds__(256) plain_kernel(KArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Shared sh = setup_shared<R, FORM_PLAIN>(a, smem);
+    const uint64_t q = a.qbegin + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < a.total) {
+        const int job = find_job(a, q, 0);
+        const JobDev &J = a.jobs[job];
+        Lane<R> p;
+        emit<R, G>(p, a, sh, J, q, job);
+        int r;
+        do {
+            r = step<R, FORM_PLAIN, G>(p, a, sh, J);
+        } while (r == 0);
+        finish<R, FORM_PLAIN>(p, a, sh, J, r == 2);
+    }
+    flush_shared(a, sh);
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
+{
+    const uint32_t lo = __shfl((uint32_t)v, src, 64);
+    const uint32_t hi = __shfl((uint32_t)(v >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename R, int G>
+__global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Shared sh = setup_shared<R, FORM_PERSISTENT>(a, smem);
+    const int lane = (int)(threadIdx.x & 63);
+    Lane<R> p;
+    bool alive = false;
+    int job = 0;
+    uint64_t pool_cur = 0, pool_end = 0;  // wave-uniform slice of the queue
+    bool exhausted = false;
+    for (;;) {
+        // refill free lanes from the queue (one atomic per wave per chunk)
+        uint64_t need = __ballot(!alive);
+        const int n_free = __popcll(need);
+        if (n_free > 0 && !exhausted && (n_free >= a.refill_min || n_free == 64)) {
+            while (need) {
+                if (pool_cur >= pool_end) {
+                    const int leader = __ffsll((unsigned long long)need) - 1;
+                    uint64_t b = 0;
+                    if (lane == leader) b = atomicAdd(a.queue, (unsigned long long)a.chunk);
+                    b = shfl64(b, leader);
+                    if (b >= a.total) {
+                        exhausted = true;
+                        break;
+                    }
+                    pool_cur = b;
+                    pool_end = (b + (uint64_t)a.chunk < a.total) ? b + (uint64_t)a.chunk : a.total;
+                }
+                const uint64_t avail = pool_end - pool_cur;
+                const int cnt = __popcll(need);
+                const int take = ((uint64_t)cnt < avail) ? cnt : (int)avail;
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+                const bool mine = ((need >> lane) & 1ull) && (int)below < take;
+                if (mine) {
+                    const uint64_t q = pool_cur + below;
+                    job = find_job(a, q, job);
+                    emit<R, G>(p, a, sh, a.jobs[job], q, job);
+                    alive = true;
+                }
+                pool_cur += (uint64_t)take;
+                need &= ~__ballot(mine);
+            }
+        }
+        if (__ballot(alive) == 0ull) break;
+        if (alive) {
+            const JobDev &J = a.jobs[job];
+            const int r = step<R, FORM_PERSISTENT, G>(p, a, sh, J);
+            if (r != 0) {
+                finish<R, FORM_PERSISTENT>(p, a, sh, J, r == 2);
+                alive = false;
+            }
+        }
+    }
+    flush_shared(a, sh);
+}
+
+__global__ void fill_kernel(double *p, size_t n, unsigned long long *q, size_t nq)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += stride) q[i] = 0ull;
+}
+
+__global__ void debug_philox_kernel(uint64_t seed, const uint64_t *pid, const uint32_t *k, const uint32_t *tag,
+                                    uint32_t *out, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 r = philox((uint32_t)pid[i], (uint32_t)(pid[i] >> 32), k[i], tag[i], (uint32_t)seed,
+                           (uint32_t)(seed >> 32));
+    out[4 * i + 0] = r.x;
+    out[4 * i + 1] = r.y;
+    out[4 * i + 2] = r.z;
+    out[4 * i + 3] = r.w;
+}
+
+__global__ void debug_alias_kernel(const uint32_t *packed, int bits, const uint32_t *words, uint32_t *states, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    states[i] = alias_draw(packed, bits, words[i]);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers ----
+
+namespace {
+
+template <typename R, int G>
+const void *kernel_ptr(int form)
+{
+    return form == FORM_PLAIN ? (const void *)plain_kernel<R, G> : (const void *)persistent_kernel<R, G>;
+}
+
+const void *pick_kernel(int precision, int form, bool slab_only)
+{
+    if (precision == 0) return slab_only ? kernel_ptr<double, GEOM_SLAB>(form) : kernel_ptr<double, GEOM_ANY>(form);
+    return slab_only ? kernel_ptr<float, GEOM_SLAB>(form) : kernel_ptr<float, GEOM_ANY>(form);
+}
+
+}  // namespace
+
+hipError_t launch_trajectories(const KArgs &a, int precision, int form, bool slab_only, int block, int grid,
+                               size_t lds_bytes, hipStream_t stream)
+{
+    const void *f = pick_kernel(precision, form, slab_only);
+    if (lds_bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    KArgs arg = a;
+    void *params[] = {&arg};
+    return hipLaunchKernel(f, dim3(grid), dim3(block), params, lds_bytes, stream);
+}
+
+hipError_t launch_fill(double *p, size_t n_doubles, unsigned long long *q, size_t n_u64, hipStream_t stream)
+{
+    const size_t n = n_doubles > n_u64 ? n_doubles : n_u64;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, p, n_doubles, q, n_u64);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_philox(uint64_t seed, const uint64_t *pid, const uint32_t *k, const uint32_t *tag,
+                               uint32_t *out, size_t n, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(debug_philox_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, seed, pid, k, tag,
+                       out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_alias(const uint32_t *packed, int bits, const uint32_t *words, uint32_t *states, size_t n,
+                              hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(debug_alias_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, packed, bits, words,
+                       states, n);
+    return hipGetLastError();
+}
+
+int max_lds_bytes() { return 160 * 1024; }
+
+int occupancy_blocks(int precision, int form, bool slab_only, int block, size_t lds_bytes)
+{
+    const void *f = pick_kernel(precision, form, slab_only);
+    if (lds_bytes > 64 * 1024) {
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return 1;
+        }
+    }
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block, lds_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return n > 0 ? n : 1;
+}
+
+}  // namespace dmc

@@ -1,0 +1,318 @@
+// dmc_server.cpp -- continuous batching of simulation requests on one device.
+//
+// Requests wait in a FIFO until a slot and enough device memory (a first-fit
+// arena carved out of one allocation made at creation) are free.  Each epoch is
+// ONE persistent launch over a slice of every admitted request's particle
+// range, so a request that arrives while others run joins at the next epoch
+// and its particles share the device with theirs.  Slices are sized so each
+// admitted request receives an equal share of the epoch's estimated flights.
+// Particles are independent and their random numbers are keyed by (seed, pid),
+// so a request's realisation does not depend on how it was sliced or with
+// which other requests it ran.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "dmc_host_internal.h"
+
+using namespace dmc;
+
+namespace {
+
+// First-fit allocator over [0, size) with coalescing; 256-byte granules.
+class Arena {
+public:
+    explicit Arena(size_t size) { free_[0] = size; }
+    bool alloc(size_t bytes, size_t &off)
+    {
+        bytes = (bytes + 255) & ~size_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                off = it->first;
+                const size_t rest = it->second - bytes;
+                free_.erase(it);
+                if (rest) free_[off + bytes] = rest;
+                used_[off] = bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off)
+    {
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        size_t start = off, len = u->second;
+        used_.erase(u);
+        auto next = free_.lower_bound(start);
+        if (next != free_.end() && start + len == next->first) {
+            len += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == start) {
+                start = prev->first;
+                len += prev->second;
+                free_.erase(prev);
+            }
+        }
+        free_[start] = len;
+    }
+
+private:
+    std::map<size_t, size_t> free_, used_;
+};
+
+struct Request {
+    uint64_t ticket = 0;
+    JobHost jh;
+    size_t bytes = 0, arena_off = 0;
+    uint64_t cursor = 0;
+    double flights_per_particle = 1.0;
+    unsigned long long stats[kStats] = {0, 0, 0, 0, 0};
+    double kernel_ms = 0.0;
+    std::vector<double> host_tally;  // filled when complete
+};
+
+}  // namespace
+
+struct dmc_server {
+    const dmc_material *M = nullptr;
+    dmc_server_opts opts{};
+    std::mutex mu;
+    void *arena_mem = nullptr;
+    std::unique_ptr<Arena> arena;
+    void *scratch = nullptr;
+    LaunchBuffers sb;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::deque<std::unique_ptr<Request>> pending;
+    std::vector<std::unique_ptr<Request>> active;
+    std::map<uint64_t, std::unique_ptr<Request>> done;
+    uint64_t next_ticket = 1;
+    ~dmc_server()
+    {
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (arena_mem) (void)hipFree(arena_mem);
+        if (scratch) (void)hipFree(scratch);
+    }
+};
+
+namespace {
+
+size_t a256(size_t x) { return (x + 255) & ~size_t(255); }
+
+double flights_estimate(const dmc_material &M, const JobHost &h)
+{
+    const JobDev &d = h.dev;
+    if (d.src == SRC_WALLS) return 2.0 * h.geom.length * M.G_tau / M.G_v + 1.0;  // mean scatters + absorption
+    if (d.src == SRC_GAUSSIAN) return h.times.back() * M.G_tau / M.C_tot + 1.0;
+    return d.kmax >= 0 ? 1.5 * d.kmax + 1.0 : 1000.0;
+}
+
+}  // namespace
+
+extern "C" dmc_status dmc_server_create(const dmc_material *material, const dmc_server_opts *opts, dmc_server **out)
+{
+    if (!out) return fail(DMC_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!material || !opts) return fail(DMC_E_INVALID, "material / opts is NULL");
+    if (opts->max_active < 1 || opts->max_active > kLdsStatJobs) return fail(DMC_E_INVALID, "max_active must be 1..64");
+    if (opts->memory_budget < 4096) return fail(DMC_E_INVALID, "memory budget too small");
+    dmc_status st = run_opts_check(opts->run);
+    if (st != DMC_OK) return st;
+    if (opts->run.workspace || opts->run.nscat_out)
+        return fail(DMC_E_INVALID, "the server manages its own device memory");
+    std::unique_ptr<dmc_server> S(new (std::nothrow) dmc_server());
+    if (!S) return fail(DMC_E_NOMEM, "host allocation failed");
+    S->M = material;
+    S->opts = *opts;
+    if (hipMalloc(&S->arena_mem, opts->memory_budget) != hipSuccess) {
+        (void)hipGetLastError();
+        S->arena_mem = nullptr;
+        return fail(DMC_E_NOMEM, "cannot allocate the server's memory budget");
+    }
+    S->arena.reset(new Arena(opts->memory_budget));
+    const size_t nj = (size_t)opts->max_active;
+    const size_t jb = a256(nj * sizeof(JobDev)), tb = a256(nj * kMaxTimes * sizeof(double)),
+                 stb = a256(nj * kStats * 8), qb = a256(16);
+    if (hipMalloc(&S->scratch, jb + tb + stb + qb) != hipSuccess) {
+        (void)hipGetLastError();
+        S->scratch = nullptr;
+        return fail(DMC_E_NOMEM, "cannot allocate server scratch");
+    }
+    char *p = (char *)S->scratch;
+    S->sb.jobs = (JobDev *)p;
+    S->sb.times = (double *)(p + jb);
+    S->sb.stats = (unsigned long long *)(p + jb + tb);
+    S->sb.queue = (unsigned long long *)(p + jb + tb + stb);
+    S->sb.tally = (double *)S->arena_mem;
+    DMC_HIP_OR_FAIL(hipEventCreate(&S->ev0));
+    DMC_HIP_OR_FAIL(hipEventCreate(&S->ev1));
+    *out = S.release();
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_server_submit(dmc_server *S, const dmc_job *job, uint64_t *ticket)
+{
+    if (!S || !job || !ticket) return fail(DMC_E_INVALID, "NULL argument");
+    *ticket = 0;
+    if (job->material != S->M) return fail(DMC_E_INVALID, "request uses another material");
+    std::unique_ptr<Request> r(new (std::nothrow) Request());
+    if (!r) return fail(DMC_E_NOMEM, "host allocation failed");
+    dmc_status st = prepare_job(*job, r->jh);
+    if (st != DMC_OK) return st;
+    r->jh.job.times = nullptr;  // the copy in jh.times is what is used
+    r->bytes = a256((size_t)std::max<int64_t>(r->jh.size, 1) * sizeof(double));
+    if (r->bytes > S->opts.memory_budget) return fail(DMC_E_INVALID, "request can never fit the memory budget");
+    r->flights_per_particle = flights_estimate(*S->M, r->jh);
+    std::lock_guard<std::mutex> g(S->mu);
+    r->ticket = S->next_ticket++;
+    *ticket = r->ticket;
+    S->pending.push_back(std::move(r));
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
+{
+    if (!S) return fail(DMC_E_INVALID, "server is NULL");
+    if (n_done) *n_done = 0;
+    hipStream_t s = (hipStream_t)S->opts.run.stream;
+    std::vector<JobDev> devs;
+    std::vector<double> times;
+    std::vector<Request *> members;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        // admit in arrival order while a slot and memory are free
+        while (!S->pending.empty() && (int)S->active.size() < S->opts.max_active) {
+            Request *r = S->pending.front().get();
+            size_t off;
+            if (!S->arena->alloc(r->bytes, off)) break;
+            r->arena_off = off;
+            DMC_HIP_OR_FAIL(launch_fill((double *)((char *)S->arena_mem + off), r->bytes / 8, nullptr, 0, s));
+            S->active.push_back(std::move(S->pending.front()));
+            S->pending.pop_front();
+        }
+        if (S->active.empty()) return DMC_OK;
+        const double epoch_flights = S->opts.epoch_flights ? (double)S->opts.epoch_flights : 2.0e10;
+        const double share = epoch_flights / (double)S->active.size();
+        uint64_t base = 0;
+        for (auto &rp : S->active) {
+            Request *r = rp.get();
+            const uint64_t left = r->jh.dev.n - r->cursor;
+            uint64_t n = (uint64_t)std::max(256.0, share / r->flights_per_particle);
+            n = std::min(n, left);
+            JobDev d = r->jh.dev;
+            const int64_t shift = (int64_t)(r->arena_off / sizeof(double));
+            if (d.off_bins >= 0) d.off_bins += shift;
+            if (d.off_kappa >= 0) d.off_kappa += shift;
+            if (d.off_hj >= 0) d.off_hj += shift;
+            if (d.off_snap >= 0) d.off_snap += shift;
+            if (d.off_snap_abs >= 0) d.off_snap_abs += shift;
+            d.base = base;
+            d.n = n;
+            d.pid0 = r->cursor;
+            d.times_off = (int32_t)times.size();
+            times.insert(times.end(), r->jh.times.begin(), r->jh.times.end());
+            base += n;
+            devs.push_back(d);
+            members.push_back(r);
+        }
+    }
+    dmc_status st = enqueue_launch(S->M, devs, times, S->sb, 0, false, S->opts.run, s, S->ev0, S->ev1);
+    if (st != DMC_OK) return st;
+    DMC_HIP_OR_FAIL(hipEventSynchronize(S->ev1));
+    float ms = 0.0f;
+    DMC_HIP_OR_FAIL(hipEventElapsedTime(&ms, S->ev0, S->ev1));
+    std::vector<unsigned long long> stats(members.size() * kStats);
+    DMC_HIP_OR_FAIL(hipMemcpy(stats.data(), S->sb.stats, stats.size() * 8, hipMemcpyDeviceToHost));
+    int32_t finished = 0;
+    std::lock_guard<std::mutex> g(S->mu);
+    for (size_t i = 0; i < members.size(); ++i) {
+        Request *r = members[i];
+        for (int k = 0; k < kStats; ++k) r->stats[k] += stats[i * kStats + k];
+        r->kernel_ms += ms;
+        r->cursor += devs[i].n;
+    }
+    for (size_t i = 0; i < S->active.size();) {
+        Request *r = S->active[i].get();
+        if (r->cursor >= r->jh.dev.n) {
+            r->host_tally.assign((size_t)std::max<int64_t>(r->jh.size, 1), 0.0);
+            DMC_HIP_OR_FAIL(hipMemcpy(r->host_tally.data(), (char *)S->arena_mem + r->arena_off,
+                                      (size_t)r->jh.size * sizeof(double), hipMemcpyDeviceToHost));
+            S->arena->release(r->arena_off);
+            S->done[r->ticket] = std::move(S->active[i]);
+            S->active.erase(S->active.begin() + (long)i);
+            ++finished;
+        } else {
+            ++i;
+        }
+    }
+    if (n_done) *n_done = finished;
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_server_poll(dmc_server *S, uint64_t ticket, int32_t *done)
+{
+    if (!S || !done) return fail(DMC_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> g(S->mu);
+    *done = S->done.count(ticket) ? 1 : 0;
+    if (*done) return DMC_OK;
+    for (auto &r : S->active)
+        if (r->ticket == ticket) return DMC_OK;
+    for (auto &r : S->pending)
+        if (r->ticket == ticket) return DMC_OK;
+    return fail(DMC_E_INVALID, "unknown ticket");
+}
+
+extern "C" dmc_status dmc_server_collect(dmc_server *S, uint64_t ticket, dmc_result **out)
+{
+    if (!S || !out) return fail(DMC_E_INVALID, "NULL argument");
+    *out = nullptr;
+    std::unique_ptr<Request> r;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        auto it = S->done.find(ticket);
+        if (it == S->done.end()) return fail(DMC_E_INVALID, "request not complete (or unknown ticket)");
+        r = std::move(it->second);
+        S->done.erase(it);
+    }
+    std::unique_ptr<dmc_result> R(new (std::nothrow) dmc_result());
+    if (!R) return fail(DMC_E_NOMEM, "host allocation failed");
+    R->mat = S->M;
+    R->jobs.push_back(r->jh);
+    R->tally_doubles = (size_t)r->jh.size;
+    R->h_tally = std::move(r->host_tally);
+    R->h_stats.assign(r->stats, r->stats + kStats);
+    R->kernel_ms = r->kernel_ms;
+    R->synced = true;
+    *out = R.release();
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_server_load(const dmc_server *cs, int32_t *queued, int32_t *running)
+{
+    dmc_server *S = const_cast<dmc_server *>(cs);
+    if (!S) return fail(DMC_E_INVALID, "server is NULL");
+    std::lock_guard<std::mutex> g(S->mu);
+    if (queued) *queued = (int32_t)S->pending.size();
+    if (running) *running = (int32_t)S->active.size();
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_server_destroy(dmc_server *S)
+{
+    if (S && S->opts.run.stream) (void)hipStreamSynchronize((hipStream_t)S->opts.run.stream);
+    else if (S) (void)hipDeviceSynchronize();
+    delete S;
+    return DMC_OK;
+}

@@ -1,0 +1,94 @@
+"""Shared helpers of the GPU tests: the parity cases (small seeded jobs that
+the FP64 oracle finishes in seconds, spanning several queue chunks and a
+ragged tail) and converters between the oracle's and the library's raw tally
+layouts."""
+from __future__ import annotations
+
+import numpy as np
+
+import dmc_inputs as di
+
+
+def small_spot(n=3000, seed=5, grid=16, n_times=8, t_max=5e-11, mat=None):
+    job = di.heated_spot(n=n, seed=seed, material=mat or di.silicon_like(), grid=grid, n_times=n_times)
+    job.tally.times = tuple(float(t) for t in np.geomspace(1e-12, t_max, n_times))
+    return job
+
+
+def mixed_slab(n=20000, seed=12, mat=None):
+    """Hot isothermal wall at z = 0, partly specular adiabatic wall at z = L."""
+    mat = mat or di.gray_material()
+    g = di.Geometry("slab_z", length=150e-9, walls=[di.Wall("isothermal", 300.5), di.Wall("adiabatic", specularity=0.5)])
+    return di.Job(mat, g, di.Source("walls"), di.Tally(n_bins=12), n, seed, "mixed_slab")
+
+
+def periodic_slab(n=4000, seed=13):
+    """Wall-emitted particles in a slab whose other walls re-insert periodically (truncated by kmax)."""
+    mat = di.gray_material()
+    g = di.Geometry("film_x", length=80e-9, walls=[di.Wall("periodic"), di.Wall("periodic")])
+    return di.Job(mat, g, di.Source("gradient", gradient=-1e6), di.Tally(n_bins=10, kmax=12, n_hj=6), n, seed,
+                  "periodic_film")
+
+
+def parity_cases():
+    si = di.silicon_like()
+    gray = di.gray_material()
+    return {
+        "gray_slab_C1": di.gray_slab(n=100_000),
+        "si_slab_100nm": di.slab_job(si, 100e-9, 20_000, seed=101, n_bins=20),
+        "si_slab_1um": di.slab_job(si, 1e-6, 2_000, seed=102, n_bins=20),
+        "mixed_slab": mixed_slab(),
+        "film_p0.5": di.in_plane_film(60e-9, 0.5, 20_000, seed=103, material=si, kmax=40, n_hj=40, n_bins=8),
+        "film_gray_p0": di.in_plane_film(100e-9, 0.0, 20_000, seed=104, material=gray, kmax=10, n_hj=10),
+        "pore_cell": di.pore_cell(100e-9, 0.3, 20_000, seed=105, material=si, kmax=40, n_hj=40),
+        "pore_cell_specular": di.pore_cell(80e-9, 0.2, 10_000, seed=106, material=gray, kmax=20, n_hj=5,
+                                           specularity=0.7),
+        "periodic_film": periodic_slab(),
+        "spot": small_spot(),
+    }
+
+
+def lib_sections(job, raw):
+    """Split a library raw tally block into the oracle's named sections."""
+    t = job.tally
+    o = 0
+    out = {}
+    if t.n_bins > 0:
+        n = t.n_batches * 3 * t.n_bins
+        out["bins"] = raw[o:o + n].reshape(t.n_batches, 3, t.n_bins)
+        o += n
+    if job.source.kind == "gradient":
+        out["kappa"] = raw[o:o + 2]
+        o += 2
+        if t.n_hj > 0:
+            out["hj"] = raw[o:o + 2 * t.n_hj].reshape(2, t.n_hj)
+            o += 2 * t.n_hj
+    if len(t.times) > 0:
+        nc = int(np.prod(t.grid)) + 1
+        nt = len(t.times)
+        out["snap"] = raw[o:o + nt * nc].reshape(nt, nc)
+        o += nt * nc
+        out["snap_abs"] = raw[o:o + nt * nc].reshape(nt, nc)
+        o += nt * nc
+    assert o == raw.shape[0], (o, raw.shape)
+    return out
+
+
+def rel_diff(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    scale = max(float(np.abs(b).max()) if b.size else 0.0, 1e-300)
+    return float(np.abs(a - b).max()) / scale if b.size else 0.0
+
+
+def compare_sections(lib_s, orc_s, rel):
+    """Largest relative difference per section (bins per quantity), and whether all are <= rel."""
+    worst = {}
+    for k, v in lib_s.items():
+        ref = orc_s[k]
+        if k == "bins":
+            for q in range(3):
+                worst[f"bins{q}"] = rel_diff(v[:, q, :], ref[:, q, :])
+        else:
+            worst[k] = rel_diff(v, ref)
+    return worst, all(w <= rel for w in worst.values())

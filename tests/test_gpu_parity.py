@@ -1,0 +1,215 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Rules (FP64 parity mode, same Philox counters as the oracle):
+  * Philox blocks and alias tables are bit-exact;
+  * per-particle scattering-event counts agree for >= 99.9 % of particles;
+  * every raw tally section agrees within 1e-9 of its largest magnitude.
+Production form (FP32 flight, FP64 tallies, persistent): every finalised
+quantity agrees within max(3 combined standard errors, 1e-3 relative).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import dmc_inputs as di
+import oracle
+from gpu_cases import compare_sections, lib_sections, parity_cases, rel_diff
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1206_3316_amd import binding as b  # noqa: E402
+
+CASES = parity_cases()
+THREADS = 16
+
+
+@pytest.fixture(scope="module")
+def oracle_runs():
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            job = CASES[name]
+            prep = oracle.prepare(job)
+            raw, cnt, ns = oracle.run_raw(job, threads=THREADS, want_nscat=True, prep=prep)
+            cache[name] = (prep, raw, cnt, ns, oracle.finalize(prep, raw))
+        return cache[name]
+
+    return get
+
+
+def run_lib(job, precision, form, **params):
+    ns = torch.zeros(job.n_particles, dtype=torch.int32, device="cuda")
+    res = b.simulate([job], precision=precision, form=form, nscat_out=ns, **params)
+    raw = res.raw(0)
+    st = res.stats(0)
+    nscat = ns.cpu().numpy().astype(np.int64)
+    return res, raw, st, nscat
+
+
+# ------------------------------------------------------------ bit-exactness ----
+
+def test_philox_bit_exact_on_device():
+    rng = np.random.Generator(np.random.PCG64(77))
+    n = 50_000
+    pid = rng.integers(0, 2 ** 63, size=n, dtype=np.uint64)
+    pid[:8] = [0, 1, 2 ** 32 - 1, 2 ** 32, 2 ** 63 - 1, 12345, 2 ** 40 + 3, 7]
+    k = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+    tag = rng.integers(0, 3, size=n, dtype=np.uint64).astype(np.uint32)
+    for seed in (0, 1, 2 ** 32 + 5, 2 ** 64 - 1):
+        dev = b.debug_philox(seed, pid, k, tag)
+        ref = np.array([oracle.rng_block(seed, int(p), int(kk), int(t)) for p, kk, t in
+                        zip(pid[:5000], k[:5000], tag[:5000])])
+        assert np.array_equal(dev[:5000], ref)
+    # the rest against the oracle's raw Philox on the same counters
+    ref = np.array([oracle.philox([int(p) & 0xFFFFFFFF, int(p) >> 32, int(kk), int(t)], [3, 0]) for p, kk, t in
+                    zip(pid, k, tag)])
+    assert np.array_equal(b.debug_philox(3, pid, k, tag), ref)
+
+
+@pytest.mark.parametrize("matname", ["gray", "silicon", "silicon_coarse"])
+def test_alias_tables_and_sums_bit_exact(matname):
+    mat = {"gray": di.gray_material(), "silicon": di.silicon_like(),
+           "silicon_coarse": di.silicon_like(n_bins=37, T_eq=77.0)}[matname]
+    lm = b.Material(mat)
+    n, sums = lm.info()
+    _, Cm, osums = oracle.tabulate(mat)
+    assert n == Cm.shape[0]
+    assert np.array_equal(sums, osums)  # identical FP64 operations in the same order
+    tau = mat.flat()[4]
+    vg = mat.flat()[3]
+    for which, w in ((b.TABLE_GAIN, Cm / tau), (b.TABLE_INIT, Cm), (b.TABLE_FLUX, Cm * vg)):
+        lt = lm.alias_table(which)
+        ot = oracle.alias(w)
+        assert lt["bits"] == ot["bits"]
+        assert np.array_equal(lt["thresh"], ot["thresh"])
+        assert np.array_equal(lt["alias"], ot["alias"])
+        # device lookups of the packed LDS/global form equal the canonical rule
+        rng = np.random.Generator(np.random.PCG64(which + 10))
+        words = rng.integers(0, 2 ** 32, size=200_000, dtype=np.uint64).astype(np.uint32)
+        U = 1 << (32 - ot["bits"])
+        edges = np.array([0, 2 ** 32 - 1, U - 1, U, 3 * U - 1] +
+                         [int(j) * U + int(t) for j, t in enumerate(ot["thresh"][:64])] +
+                         [int(j) * U + max(int(t) - 1, 0) for j, t in enumerate(ot["thresh"][:64])], dtype=np.uint64)
+        words = np.concatenate([words, (edges % 2 ** 32).astype(np.uint32)])
+        assert np.array_equal(lm.alias_draw(which, words).astype(np.int64), oracle.alias_draw(ot, words))
+
+
+# --------------------------------------------------------- FP64 parity mode ----
+
+@pytest.mark.parametrize("form", ["plain", "persistent"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_parity_with_oracle(name, form, oracle_runs):
+    job = CASES[name]
+    prep, oraw, ocnt, ons, _ = oracle_runs(name)
+    print(f"case {name} form {form} n {job.n_particles}", flush=True)
+    res, raw, st, nscat = run_lib(job, "fp64", form)
+    agree = float(np.mean(nscat == ons))
+    assert agree >= 0.999, agree
+    worst, ok = compare_sections(lib_sections(job, raw), oracle.split_raw(prep, oraw), 1e-9)
+    assert ok, worst
+    assert st.particles == job.n_particles
+    assert st.scatters == int(ons.sum()) or agree < 1.0
+    assert st.capped == 0
+
+
+# ----------------------------------------------- production FP32 tolerance ----
+
+def _assert_stat_close(name, q, got, got_se, ref, ref_se, floor=1e-3):
+    got, ref = np.atleast_1d(got), np.atleast_1d(ref)
+    comb = np.sqrt(np.atleast_1d(got_se) ** 2 + np.atleast_1d(ref_se) ** 2)
+    tol = np.maximum(3.0 * comb, floor * np.abs(ref))
+    bad = np.abs(got - ref) > tol
+    assert not bad.any(), (name, q, got[bad], ref[bad], tol[bad])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp32_production_within_tolerance(name, oracle_runs):
+    job = CASES[name]
+    prep, oraw, ocnt, ons, ores = oracle_runs(name)
+    print(f"case {name} fp32 persistent", flush=True)
+    res = b.simulate([job], precision="fp32", form="persistent")
+    t = job.tally
+    if t.n_bins > 0:
+        for q, key in ((b.Q_T, "T"), (b.Q_TLOC, "Tloc"), (b.Q_FLUX, "q")):
+            m, se = res.read(0, q)
+            _assert_stat_close(name, key, m, se, ores[key], ores[key + "_se"])
+    if job.source.kind == "gradient":
+        m, se = res.read(0, b.Q_KAPPA)
+        _assert_stat_close(name, "kappa", m, se, ores["kappa"], ores["kappa_se"])
+        if t.n_hj > 0:
+            m, se = res.read(0, b.Q_HJ)
+            _assert_stat_close(name, "hj", m, se, ores["hj"], ores["hj_se"])
+    if len(t.times) > 0:
+        for ti in range(len(t.times)):
+            m, se = res.read(0, b.Q_SNAPSHOT, ti)
+            _assert_stat_close(name, f"snap{ti}", m, se, ores["snap_T"][ti], ores["snap_T_se"][ti])
+            s, _ = res.read(0, b.Q_SNAPSHOT_SUM, ti)
+            assert s.sum() == job.n_particles  # particles are conserved at every snapshot
+    st = res.stats(0)
+    assert st.particles == job.n_particles and st.capped == 0
+
+
+# ------------------------------------------------------------- edge cases ----
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 4097])
+@pytest.mark.parametrize("form", ["plain", "persistent"])
+def test_ragged_sizes_fp64(n, form):
+    """Tiny and ragged particle counts across chunk boundaries (chunk = 64 particles)."""
+    job = di.slab_job(di.silicon_like(), 100e-9, n, seed=300 + n, n_bins=20)
+    prep = oracle.prepare(job)
+    oraw, ocnt, ons = oracle.run_raw(job, threads=4, want_nscat=True, prep=prep)
+    ns = torch.zeros(n, dtype=torch.int32, device="cuda")
+    res = b.simulate([job], precision="fp64", form=form, nscat_out=ns, chunk=64, refill_min=1)
+    worst, ok = compare_sections(lib_sections(job, res.raw(0)), oracle.split_raw(prep, oraw), 1e-9)
+    assert ok, worst
+    assert np.mean(ns.cpu().numpy() == ons) >= 0.999
+    assert res.stats(0).particles == n
+
+
+def test_batch_equals_solo_and_parameter_invariance():
+    """One persistent launch of mixed jobs gives each job the tallies of its solo
+    run (same per-particle arithmetic, FP64 sums in another order); queue chunk,
+    refill threshold, block size and tally privatisation do not change results."""
+    si = di.silicon_like()
+    jobs = [di.slab_job(si, 50e-9, 30_000, seed=401, n_bins=20),
+            di.in_plane_film(40e-9, 0.9, 20_000, seed=402, material=si, kmax=40, n_hj=10),
+            di.pore_cell(60e-9, 0.2, 25_000, seed=403, material=si, kmax=40, n_hj=10),
+            small_spot_job(),
+            di.slab_job(si, 300e-9, 7_000, seed=404, n_bins=20)]
+    mat = b.Material(si)
+    batch = b.simulate(jobs, material=mat)
+    for j, job in enumerate(jobs):
+        solo = b.simulate([job], material=mat)
+        assert rel_diff(batch.raw(j), solo.raw(0)) <= 1e-12, job.name
+        s1, s2 = batch.stats(j), solo.stats(0)
+        assert (s1.particles, s1.scatters, s1.boundary, s1.iterations) == (s2.particles, s2.scatters, s2.boundary,
+                                                                           s2.iterations)
+    ref = batch
+    for params in ({"chunk": 64, "refill_min": 1}, {"chunk": 4096, "refill_min": 48, "block": 256},
+                   {"lds_tally": 0, "block": 1024}, {"grid_blocks": 7}):
+        other = b.simulate(jobs, material=mat, **params)
+        for j in range(len(jobs)):
+            assert rel_diff(other.raw(j), ref.raw(j)) <= 1e-12, (params, j)
+
+
+def small_spot_job():
+    from gpu_cases import small_spot
+    return small_spot(n=2000, seed=406, grid=8, n_times=4)
+
+
+def test_invalid_jobs_are_rejected():
+    si = di.silicon_like()
+    job = di.slab_job(si, 100e-9, 10, seed=1)
+    job.tally.n_hj = 3  # needs kmax
+    with pytest.raises(b.DmcError):
+        b.simulate([job])
+    job = di.in_plane_film(50e-9, 0.0, 10, seed=1, material=si)
+    job.source.gradient = 0.0
+    with pytest.raises(b.DmcError):
+        b.simulate([job])
