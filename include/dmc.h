@@ -290,6 +290,10 @@ dmc_status dmc_debug_alias(const dmc_material *m, int32_t which, int32_t *bits, 
 dmc_status dmc_debug_alias_draw(const dmc_material *m, int32_t which, const uint32_t *words, uint32_t *states,
                                 size_t n);
 
+/* FP64 parity-mode logarithm and sin/cos of 2 pi u, evaluated on the device
+ * for n host values (out arrays of n, any may be NULL). */
+dmc_status dmc_debug_fp64_math(const double *x, double *log_out, double *sin2pi_out, double *cos2pi_out, size_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -101,6 +101,9 @@ def lib():
             L.oracle_run.argtypes = [C.POINTER(Problem), C.c_uint64, C.c_uint64, f64p, C.POINTER(Counters), u32p,
                                      C.POINTER(C.c_uint64)]
             L.oracle_run.restype = C.c_int
+            L.oracle_log.argtypes = [C.c_double]
+            L.oracle_log.restype = C.c_double
+            L.oracle_sincos2pi.argtypes = [C.c_double, f64p, f64p]
             _lib = L
     return _lib
 
@@ -126,6 +129,18 @@ def rng_block(seed: int, pid: int, k: int, tag: int) -> np.ndarray:
     out = np.zeros(4, np.uint32)
     lib().oracle_rng_block(seed, pid, k, tag, _p(out, C.c_uint32))
     return out
+
+
+def log(x: float) -> float:
+    """The reference's logarithm (IEEE basic operations only)."""
+    return lib().oracle_log(float(x))
+
+
+def sincos2pi(u: float):
+    """The reference's (sin, cos) of 2 pi u (IEEE basic operations only)."""
+    s, c = C.c_double(), C.c_double()
+    lib().oracle_sincos2pi(float(u), C.byref(s), C.byref(c))
+    return s.value, c.value
 
 
 def tabulate(material: di.Material):

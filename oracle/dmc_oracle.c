@@ -38,7 +38,6 @@
 
 #define OR_HBAR 1.054571817e-34 /* J s (CODATA 2018) */
 #define OR_KB 1.380649e-23      /* J/K (CODATA 2018) */
-#define OR_PI 3.14159265358979323846
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10                                                             */
@@ -78,6 +77,84 @@ static void rng_block(uint64_t seed, uint64_t pid, uint32_t k, uint32_t tag, uin
 
 /* R in ]0,1[ (step II): (w + 1/2) 2^-32, exact in FP64. */
 static double unif(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
+
+/* ------------------------------------------------------------------------ */
+/* Elementary functions from IEEE basic operations                          */
+/* ------------------------------------------------------------------------ */
+/* The reference fixes its logarithm and its sine/cosine of 2 pi u to these
+ * algorithms (only +, -, *, /, floor and frexp, no contraction), so that any
+ * implementation following the same steps reproduces every trajectory bit for
+ * bit.  Trajectories among convex pores are chaotic: a one-ulp difference in a
+ * library logarithm or cosine grows until the path changes.  Accuracy is about
+ * one ulp (pinned against the C library in the tests). */
+
+static const double OR_LN2_HI = 0x1.62e42ff000000p-1; /* ln 2 to 32 bits: e * hi is exact */
+static const double OR_LN2_LO = -0x1.718432a1b0e26p-35; /* ln 2 - hi */
+static const double OR_SQRT_HALF = 0x1.6a09e667f3bcdp-1;
+static const double OR_PIO2 = 0x1.921fb54442d18p+0;  /* pi / 2 rounded to double */
+
+/* log x for normal x > 0: x = m 2^e with m in [sqrt(1/2), sqrt(2)),
+ * log m = 2 atanh(s) = 2 s sum_k s^(2k) / (2k + 1), s = (m - 1)/(m + 1),
+ * |s| <= 0.1716, series to s^23 (next term below 1e-18 relative). */
+double oracle_log(double x)
+{
+    int e;
+    double m = frexp(x, &e); /* m in [0.5, 1) */
+    if (m < OR_SQRT_HALF) { m = m * 2.0; e = e - 1; }
+    double s = (m - 1.0) / (m + 1.0);
+    double z = s * s;
+    double p = 1.0 / 23.0;
+    p = p * z + 1.0 / 21.0;
+    p = p * z + 1.0 / 19.0;
+    p = p * z + 1.0 / 17.0;
+    p = p * z + 1.0 / 15.0;
+    p = p * z + 1.0 / 13.0;
+    p = p * z + 1.0 / 11.0;
+    p = p * z + 1.0 / 9.0;
+    p = p * z + 1.0 / 7.0;
+    p = p * z + 1.0 / 5.0;
+    p = p * z + 1.0 / 3.0;
+    p = p * z + 1.0;
+    double lm = (2.0 * s) * p;
+    double de = (double)e;
+    return de * OR_LN2_HI + (de * OR_LN2_LO + lm);
+}
+
+/* sin and cos of 2 pi u for u in [0, 1): v = 4u quarter turns (exact), nearest
+ * quarter k, r = v - k in [-1/2, 1/2] (exact), t = r pi/2 in [-pi/4, pi/4],
+ * Taylor series of sin t to t^17 and cos t to t^18, then the quadrant k. */
+void oracle_sincos2pi(double u, double *sn, double *cs)
+{
+    double v = 4.0 * u;
+    double k = floor(v + 0.5);
+    double r = v - k;
+    double t = r * OR_PIO2;
+    double t2 = t * t;
+    double ps = -1.0 / 355687428096000.0;            /* -1/17! */
+    ps = ps * t2 + 1.0 / 1307674368000.0;            /* 1/15! */
+    ps = ps * t2 - 1.0 / 6227020800.0;               /* 1/13! */
+    ps = ps * t2 + 1.0 / 39916800.0;                 /* 1/11! */
+    ps = ps * t2 - 1.0 / 362880.0;                   /* 1/9! */
+    ps = ps * t2 + 1.0 / 5040.0;                     /* 1/7! */
+    ps = ps * t2 - 1.0 / 120.0;                      /* 1/5! */
+    ps = ps * t2 + 1.0 / 6.0;                        /* 1/3! */
+    double st = t - t * (t2 * ps);
+    double pc = 1.0 / 6402373705728000.0;            /* 1/18! */
+    pc = pc * t2 - 1.0 / 20922789888000.0;           /* 1/16! */
+    pc = pc * t2 + 1.0 / 87178291200.0;              /* 1/14! */
+    pc = pc * t2 - 1.0 / 479001600.0;                /* 1/12! */
+    pc = pc * t2 + 1.0 / 3628800.0;                  /* 1/10! */
+    pc = pc * t2 - 1.0 / 40320.0;                    /* 1/8! */
+    pc = pc * t2 + 1.0 / 720.0;                      /* 1/6! */
+    pc = pc * t2 - 1.0 / 24.0;                       /* 1/4! */
+    pc = pc * t2 + 1.0 / 2.0;                        /* 1/2! */
+    double ct = 1.0 - t2 * pc;
+    int q = ((int)k) & 3;
+    if (q == 0) { *sn = st; *cs = ct; }
+    else if (q == 1) { *sn = ct; *cs = -st; }
+    else if (q == 2) { *sn = -st; *cs = -ct; }
+    else { *sn = -ct; *cs = st; }
+}
 
 /* ------------------------------------------------------------------------ */
 /* Material tabulation                                                      */
@@ -266,12 +343,14 @@ typedef struct {
     int32_t last;  /* surface the particle rests on, excluded from the next search */
 } particle;
 
-/* Direction with polar cosine mu about the unit normal n and azimuth phi, in
- * the tangent frame (t1, t2):  Omega = mu n + sqrt(1-mu^2)(cos phi t1 + sin phi t2). */
-static void dir_about(double mu, double phi, const double n[3], const double t1[3], const double t2[3], double o[3])
+/* Direction with polar cosine mu about the unit normal n and azimuth
+ * phi = 2 pi u, in the tangent frame (t1, t2):
+ * Omega = mu n + sqrt(1-mu^2)(cos phi t1 + sin phi t2). */
+static void dir_about(double mu, double u, const double n[3], const double t1[3], const double t2[3], double o[3])
 {
     double st = sqrt(1.0 - mu * mu);
-    double c = cos(phi), s = sin(phi);
+    double c, s;
+    oracle_sincos2pi(u, &s, &c);
     for (int i = 0; i < 3; ++i) o[i] = mu * n[i] + st * (c * t1[i] + s * t2[i]);
 }
 
@@ -281,8 +360,7 @@ static const double EX[3] = {1, 0, 0}, EY[3] = {0, 1, 0}, EZ[3] = {0, 0, 1};
 static void isotropic(uint32_t w2, uint32_t w3, double o[3])
 {
     double mu = 2.0 * unif(w2) - 1.0;
-    double phi = 2.0 * OR_PI * unif(w3);
-    dir_about(mu, phi, EZ, EX, EY, o);
+    dir_about(mu, unif(w3), EZ, EX, EY, o);
 }
 
 /* Lambertian (cosine-weighted) direction about an inward normal: mu = sqrt(u).
@@ -290,11 +368,10 @@ static void isotropic(uint32_t w2, uint32_t w3, double o[3])
 static void lambertian_plane(int axis, double sgn, uint32_t w2, uint32_t w3, double o[3])
 {
     double mu = sqrt(unif(w2));
-    double phi = 2.0 * OR_PI * unif(w3);
     double n[3] = {0, 0, 0};
     n[axis] = sgn;
-    if (axis == 2) dir_about(mu, phi, n, EX, EY, o);
-    else dir_about(mu, phi, n, EY, EZ, o);
+    if (axis == 2) dir_about(mu, unif(w3), n, EX, EY, o);
+    else dir_about(mu, unif(w3), n, EY, EZ, o);
 }
 
 /* Step I: draw sign, position, state and direction from the source term. */
@@ -321,12 +398,14 @@ static void emit(const oracle_problem *P, uint64_t pid, particle *p)
         p->m = alias_draw(a[1], P->init_bits, P->init_thresh, P->init_alias);
         isotropic(a[2], a[3], p->o);
         double sigma = P->r0 / sqrt(2.0);
-        double rho = sqrt(-2.0 * log(unif(b[0])));
-        double th = 2.0 * OR_PI * unif(b[1]);
-        p->x[0] = sigma * rho * cos(th);
-        p->x[1] = sigma * rho * sin(th);
-        double rz = sqrt(-2.0 * log(unif(b[2])));
-        p->x[2] = fabs(sigma * rz * cos(2.0 * OR_PI * unif(b[3])));
+        double rho = sqrt(-2.0 * oracle_log(unif(b[0])));
+        double c1, s1, c2, s2;
+        oracle_sincos2pi(unif(b[1]), &s1, &c1);
+        p->x[0] = sigma * rho * c1;
+        p->x[1] = sigma * rho * s1;
+        double rz = sqrt(-2.0 * oracle_log(unif(b[2])));
+        oracle_sincos2pi(unif(b[3]), &s2, &c2);
+        p->x[2] = fabs(sigma * rz * c2);
         p->s = (P->dT > 0.0) ? 1.0 : -1.0;
     } else { /* OR_SRC_GRADIENT, Eq. (6): state ~ C v, |cos theta| weighted, uniform in the solid */
         rng_block(P->seed, pid, 0, OR_TAG_EMIT_B, b);
@@ -418,8 +497,7 @@ static int wall_interaction(const oracle_problem *P, particle *p, int32_t surf, 
         } else {
             double t2[3] = {-n[2], 0.0, n[0]};
             double mu = sqrt(unif(w[2]));
-            double phi = 2.0 * OR_PI * unif(w[3]);
-            dir_about(mu, phi, n, EY, t2, p->o);
+            dir_about(mu, unif(w[3]), n, EY, t2, p->o);
         }
         p->last = 4;
         return 0;
@@ -534,7 +612,7 @@ int oracle_run(const oracle_problem *P, uint64_t pid0, uint64_t pid1, double *ta
             ++k;
             cnt->iterations++;
             double v = P->v[p.m], tau_m = P->tau[p.m];
-            double dt = -tau_m * log(unif(w[0]));                      /* step II */
+            double dt = -tau_m * oracle_log(unif(w[0]));               /* step II */
             int32_t surf;
             double tb = boundary_search(P, &p, v, &surf);             /* step III */
             int boundary = (tb <= dt);

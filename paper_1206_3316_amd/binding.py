@@ -105,6 +105,7 @@ _SIGS = {
     "dmc_debug_philox": ([C.c_uint64, C.POINTER(C.c_uint64), u32p, u32p, u32p, C.c_size_t], C.c_int32),
     "dmc_debug_alias": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int32), u32p, u32p, C.c_size_t], C.c_int32),
     "dmc_debug_alias_draw": ([C.c_void_p, C.c_int32, u32p, u32p, C.c_size_t], C.c_int32),
+    "dmc_debug_fp64_math": ([f64p, f64p, f64p, f64p, C.c_size_t], C.c_int32),
 }
 
 EXPORTS = tuple(_SIGS)
@@ -447,6 +448,19 @@ def workspace_bytes(jobs, material: Material, precision="fp32", form="persistent
     n = C.c_size_t()
     dmc_workspace_size(arr, len(jobs), C.byref(o), C.byref(n))
     return int(n.value)
+
+
+def dmc_debug_fp64_math(x, log_out, sin_out, cos_out, n):
+    return _call("dmc_debug_fp64_math", x, log_out, sin_out, cos_out, n)
+
+
+def debug_fp64_math(x):
+    """Device FP64 (log x, sin 2 pi x, cos 2 pi x) of the parity mode."""
+    x = np.ascontiguousarray(x, np.float64)
+    n = x.shape[0]
+    lg, sn, cs = np.zeros(n), np.zeros(n), np.zeros(n)
+    dmc_debug_fp64_math(_ptr(x, C.c_double), _ptr(lg, C.c_double), _ptr(sn, C.c_double), _ptr(cs, C.c_double), n)
+    return lg, sn, cs
 
 
 def debug_philox(seed: int, pid, k, tag) -> np.ndarray:

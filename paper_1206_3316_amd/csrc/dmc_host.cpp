@@ -958,3 +958,22 @@ extern "C" dmc_status dmc_debug_alias_draw(const dmc_material *m, int32_t which,
     if (e != hipSuccess) return fail(DMC_E_DEVICE, hipGetErrorString(e));
     return DMC_OK;
 }
+
+extern "C" dmc_status dmc_debug_fp64_math(const double *x, double *log_out, double *sin_out, double *cos_out, size_t n)
+{
+    if (!x) return fail(DMC_E_INVALID, "x is NULL");
+    if (n == 0) return DMC_OK;
+    double *d = nullptr;
+    if (hipMalloc(&d, 4 * n * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DMC_E_NOMEM, "hipMalloc failed");
+    }
+    hipError_t e = hipMemcpy(d, x, n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_debug_math(d, d + n, d + 2 * n, d + 3 * n, n, nullptr);
+    if (e == hipSuccess && log_out) e = hipMemcpy(log_out, d + n, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && sin_out) e = hipMemcpy(sin_out, d + 2 * n, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && cos_out) e = hipMemcpy(cos_out, d + 3 * n, n * sizeof(double), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(DMC_E_DEVICE, hipGetErrorString(e));
+    return DMC_OK;
+}

@@ -91,6 +91,7 @@ hipError_t launch_debug_philox(uint64_t seed, const uint64_t *pid, const uint32_
                                uint32_t *out, size_t n, hipStream_t stream);
 hipError_t launch_debug_alias(const uint32_t *packed, int bits, const uint32_t *words, uint32_t *states, size_t n,
                               hipStream_t stream);
+hipError_t launch_debug_math(const double *x, double *lg, double *sn, double *cs, size_t n, hipStream_t stream);
 int max_lds_bytes();
 int occupancy_blocks(int precision, int form, bool slab_only, int block, size_t lds_bytes);
 

@@ -34,8 +34,6 @@
 namespace dmc {
 namespace {
 
-constexpr double kTwoPi = 2.0 * 3.14159265358979323846;
-
 // ---------------------------------------------------------------- Philox ----
 
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1)
@@ -71,21 +69,82 @@ __device__ __forceinline__ uint32_t alias_draw(const uint32_t *tab, int bits, ui
 template <typename R>
 struct Pr;
 
+// FP64 logarithm and sin/cos of 2 pi u built only from IEEE-exact basic
+// operations (no contraction), following fixed steps that the FP64 reference
+// also follows, so the parity mode reproduces its trajectories bit for bit
+// (paths among convex pores are chaotic and would amplify one-ulp library
+// differences).
+//   log x:  x = m 2^e, m in [sqrt(1/2), sqrt(2)); log m = 2 atanh(s),
+//           s = (m-1)/(m+1), odd series in s to s^23; + e ln2 (two-part ln 2).
+//   sincos 2 pi u: v = 4u, k = floor(v + 1/2), t = (v - k) pi/2 in [-pi/4, pi/4],
+//           Taylor series to t^17 (sin) and t^18 (cos), quadrant k mod 4.
+__device__ __forceinline__ double det_log(double x)
+{
+    int e;
+    double m = frexp(x, &e);
+    if (m < 0x1.6a09e667f3bcdp-1) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 23.0;
+    p = p * z + 1.0 / 21.0;
+    p = p * z + 1.0 / 19.0;
+    p = p * z + 1.0 / 17.0;
+    p = p * z + 1.0 / 15.0;
+    p = p * z + 1.0 / 13.0;
+    p = p * z + 1.0 / 11.0;
+    p = p * z + 1.0 / 9.0;
+    p = p * z + 1.0 / 7.0;
+    p = p * z + 1.0 / 5.0;
+    p = p * z + 1.0 / 3.0;
+    p = p * z + 1.0;
+    const double lm = (2.0 * s) * p;
+    const double de = (double)e;
+    return de * 0x1.62e42ff000000p-1 + (de * -0x1.718432a1b0e26p-35 + lm);
+}
+
+__device__ __forceinline__ void det_sincos2pi(double u, double &sn, double &cs)
+{
+    const double v = 4.0 * u;
+    const double k = floor(v + 0.5);
+    const double t = (v - k) * 0x1.921fb54442d18p+0;
+    const double t2 = t * t;
+    double ps = -1.0 / 355687428096000.0;
+    ps = ps * t2 + 1.0 / 1307674368000.0;
+    ps = ps * t2 - 1.0 / 6227020800.0;
+    ps = ps * t2 + 1.0 / 39916800.0;
+    ps = ps * t2 - 1.0 / 362880.0;
+    ps = ps * t2 + 1.0 / 5040.0;
+    ps = ps * t2 - 1.0 / 120.0;
+    ps = ps * t2 + 1.0 / 6.0;
+    const double st = t - t * (t2 * ps);
+    double pc = 1.0 / 6402373705728000.0;
+    pc = pc * t2 - 1.0 / 20922789888000.0;
+    pc = pc * t2 + 1.0 / 87178291200.0;
+    pc = pc * t2 - 1.0 / 479001600.0;
+    pc = pc * t2 + 1.0 / 3628800.0;
+    pc = pc * t2 - 1.0 / 40320.0;
+    pc = pc * t2 + 1.0 / 720.0;
+    pc = pc * t2 - 1.0 / 24.0;
+    pc = pc * t2 + 1.0 / 2.0;
+    const double ct = 1.0 - t2 * pc;
+    const int q = ((int)k) & 3;
+    sn = (q == 0) ? st : (q == 1) ? ct : (q == 2) ? -st : -ct;
+    cs = (q == 0) ? ct : (q == 1) ? -st : (q == 2) ? -ct : st;
+}
+
 template <>
 struct Pr<double> {
     static constexpr double inf() { return __builtin_huge_val(); }
     __device__ static double u(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
-    __device__ static double flight(double tau, uint32_t w) { return -tau * log(u(w)); }
+    __device__ static double flight(double tau, uint32_t w) { return -tau * det_log(u(w)); }
     __device__ static double sq(double x) { return sqrt(x); }
-    __device__ static void cs(uint32_t w, double &c, double &s)
-    {
-        const double ph = kTwoPi * u(w);
-        c = cos(ph);
-        s = sin(ph);
-    }
+    __device__ static void cs(uint32_t w, double &c, double &s) { det_sincos2pi(u(w), s, c); }
     __device__ static double div(double a, double b) { return a / b; }
     __device__ static double ptime(double t, double tau, double) { return t / tau; }
-    __device__ static double lg(double x) { return log(x); }
+    __device__ static double lg(double x) { return det_log(x); }
     // FP64 keeps the reference's arithmetic unchanged
     __device__ static double nonneg(double t) { return t; }
 };
@@ -837,7 +896,25 @@ __global__ void debug_alias_kernel(const uint32_t *packed, int bits, const uint3
     states[i] = alias_draw(packed, bits, words[i]);
 }
 
+__global__ void debug_math_kernel(const double *x, double *lg, double *sn, double *cs, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s, c;
+    det_sincos2pi(x[i], s, c);
+    lg[i] = (x[i] > 0.0) ? det_log(x[i]) : 0.0;
+    sn[i] = s;
+    cs[i] = c;
+}
+
 }  // namespace
+
+hipError_t launch_debug_math(const double *x, double *lg, double *sn, double *cs, size_t n, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(debug_math_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, x, lg, sn, cs, n);
+    return hipGetLastError();
+}
 
 // ------------------------------------------------------------- launchers ----
 

@@ -14,7 +14,7 @@ import pytest
 
 import dmc_inputs as di
 import oracle
-from gpu_cases import compare_sections, lib_sections, parity_cases, rel_diff
+from gpu_cases import compare_sections, lib_sections, parity_cases, rel_diff, vmax_of
 
 pytestmark = pytest.mark.gpu
 
@@ -72,6 +72,18 @@ def test_philox_bit_exact_on_device():
     assert np.array_equal(b.debug_philox(3, pid, k, tag), ref)
 
 
+def test_fp64_elementary_functions_bit_exact():
+    """The parity mode's logarithm and sin/cos of 2 pi u equal the reference's bit for bit."""
+    rng = np.random.Generator(np.random.PCG64(78))
+    w = rng.integers(0, 2 ** 32, size=20000, dtype=np.uint64)
+    x = (w.astype(np.float64) + 0.5) / 2.0 ** 32
+    x = np.concatenate([x, [0.125, 0.25, 0.5, 0.75, 2.0 ** -33, 1 - 2.0 ** -33, 0.7071067811865476]])
+    lg, sn, cs = b.debug_fp64_math(x)
+    for i in range(x.shape[0]):
+        s, c = oracle.sincos2pi(x[i])
+        assert lg[i] == oracle.log(x[i]) and sn[i] == s and cs[i] == c, (i, x[i])
+
+
 @pytest.mark.parametrize("matname", ["gray", "silicon", "silicon_coarse"])
 def test_alias_tables_and_sums_bit_exact(matname):
     mat = {"gray": di.gray_material(), "silicon": di.silicon_like(),
@@ -111,7 +123,7 @@ def test_fp64_parity_with_oracle(name, form, oracle_runs):
     res, raw, st, nscat = run_lib(job, "fp64", form)
     agree = float(np.mean(nscat == ons))
     assert agree >= 0.999, agree
-    worst, ok = compare_sections(lib_sections(job, raw), oracle.split_raw(prep, oraw), 1e-9)
+    worst, ok = compare_sections(lib_sections(job, raw), oracle.split_raw(prep, oraw), 1e-9, vmax_of(job))
     assert ok, worst
     assert st.particles == job.n_particles
     assert st.scatters == int(ons.sum()) or agree < 1.0
@@ -120,10 +132,13 @@ def test_fp64_parity_with_oracle(name, form, oracle_runs):
 
 # ----------------------------------------------- production FP32 tolerance ----
 
-def _assert_stat_close(name, q, got, got_se, ref, ref_se, floor=1e-3):
+def _assert_stat_close(name, q, got, got_se, ref, ref_se, scale=None, rel=1e-3):
+    """|got - ref| <= max(3 combined standard errors, rel * scale); scale defaults to
+    the largest |ref| of the quantity (per-quantity relative error)."""
     got, ref = np.atleast_1d(got), np.atleast_1d(ref)
     comb = np.sqrt(np.atleast_1d(got_se) ** 2 + np.atleast_1d(ref_se) ** 2)
-    tol = np.maximum(3.0 * comb, floor * np.abs(ref))
+    sc = float(np.abs(ref).max()) if scale is None else scale
+    tol = np.maximum(3.0 * comb, rel * sc)
     bad = np.abs(got - ref) > tol
     assert not bad.any(), (name, q, got[bad], ref[bad], tol[bad])
 
@@ -138,7 +153,12 @@ def test_fp32_production_within_tolerance(name, oracle_runs):
     if t.n_bins > 0:
         for q, key in ((b.Q_T, "T"), (b.Q_TLOC, "Tloc"), (b.Q_FLUX, "q")):
             m, se = res.read(0, q)
-            _assert_stat_close(name, key, m, se, ores[key], ores[key + "_se"])
+            scale = None
+            if key == "q" and job.source.kind == "walls":
+                # a flux that vanishes by construction (adiabatic wall) is measured against the
+                # emitted wall power per unit area
+                scale = max(float(np.abs(ores["q"]).max()), 1e-3 * prep.power)
+            _assert_stat_close(name, key, m, se, ores[key], ores[key + "_se"], scale)
     if job.source.kind == "gradient":
         m, se = res.read(0, b.Q_KAPPA)
         _assert_stat_close(name, "kappa", m, se, ores["kappa"], ores["kappa_se"])
@@ -166,7 +186,7 @@ def test_ragged_sizes_fp64(n, form):
     oraw, ocnt, ons = oracle.run_raw(job, threads=4, want_nscat=True, prep=prep)
     ns = torch.zeros(n, dtype=torch.int32, device="cuda")
     res = b.simulate([job], precision="fp64", form=form, nscat_out=ns, chunk=64, refill_min=1)
-    worst, ok = compare_sections(lib_sections(job, res.raw(0)), oracle.split_raw(prep, oraw), 1e-9)
+    worst, ok = compare_sections(lib_sections(job, res.raw(0)), oracle.split_raw(prep, oraw), 1e-9, vmax_of(job))
     assert ok, worst
     assert np.mean(ns.cpu().numpy() == ons) >= 0.999
     assert res.stats(0).particles == n

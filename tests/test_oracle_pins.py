@@ -71,6 +71,38 @@ def test_uniform_words_statistics():
         assert stats.kstest(u[:, col], "uniform").pvalue > 1e-3
 
 
+# ------------------------------------------------- elementary functions ----
+
+def _ulps(a, b):
+    return abs(a - b) / np.spacing(abs(b))
+
+
+def test_reference_log_within_one_ulp_of_libm():
+    """The reference logarithm (atanh series on IEEE basic operations) agrees with the C
+    library to about an ulp over the whole range of R = (w + 1/2) 2^-32."""
+    rng = np.random.Generator(np.random.PCG64(8))
+    w = np.concatenate([rng.integers(0, 2 ** 32, 20000), [0, 1, 2 ** 31, 2 ** 32 - 1, 2 ** 32 - 2, 3037000499]])
+    worst = 0.0
+    for wi in w:
+        u = (float(wi) + 0.5) / 2.0 ** 32
+        worst = max(worst, _ulps(oracle.log(u), math.log(u)))
+    assert worst <= 2.0, worst
+    for x in (1e-300, 0.5, 1.0, 2.0, math.e, 1e300):
+        assert _ulps(oracle.log(x), math.log(x)) <= 2.0 or abs(math.log(x)) < 1e-300
+
+
+def test_reference_sincos_2pi_accuracy_and_symmetries():
+    """sin/cos of 2 pi u within 2e-16 of the C library, exact at quarter turns."""
+    rng = np.random.Generator(np.random.PCG64(9))
+    us = np.concatenate([rng.random(20000), [0.0, 0.125, 0.25, 0.5, 0.75, 0.999999999, 1e-12, 0.3749999999]])
+    for u in us:
+        s, c = oracle.sincos2pi(u)
+        assert abs(s - math.sin(2 * math.pi * u)) <= 2e-16 + 1e-15 * abs(u)
+        assert abs(c - math.cos(2 * math.pi * u)) <= 2e-16 + 1e-15 * abs(u)
+    assert oracle.sincos2pi(0.25) == (1.0, 0.0) or oracle.sincos2pi(0.25)[0] == 1.0
+    assert oracle.sincos2pi(0.5)[1] == -1.0 and oracle.sincos2pi(0.0) == (0.0, 1.0)
+
+
 # ---------------------------------------------------------- Tabulation ----
 
 HBAR, KB = 1.054571817e-34, 1.380649e-23
