@@ -29,19 +29,22 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic VALU work of one flight of the cross-plane slab path, in
-# full-rate lane-operation equivalents (a quarter-rate instruction counts 4):
-#   Philox4x32-10: 10 rounds x (2 32x32->64 multiplies @4 + 2 three-way xors
-#                  + 2 key additions)                                       = 120
-#   three word -> uniform conversions (shift, convert, scale)                =   9
-#   -ln u (log2 @4 + scale), flight time                                     =   6
-#   wall distance, reciprocal @4, hit compare and select                     =  10
-#   position update                                                          =   2
-#   two bin indices (scale, floor, convert, clamp)                           =  10
-#   three FP64 tally accumulations with FP32 -> FP64 conversions             =   9
-#   gain alias draw (shift, mask, compare, select), mu = 2u - 1              =   6
-#   loop control and event bookkeeping                                       =   4
-OPS_PER_FLIGHT = 176
+# Algorithmic VALU work of one flight of the cross-plane slab path, counted in
+# full-rate VALU issue slots per lane (the MI355X issues 64 lane-slots per CU
+# per clock).  Instruction costs on gfx950 were measured with a throughput
+# probe: a Philox4x32-10 block (20 32x32->64 multiply-adds, 20 xors, 18 key
+# additions) takes 57 lane-slots; v_log_f32 takes 2.
+#   Philox4x32-10 block                                                  57
+#   two word -> uniform conversions (shift, convert, add 1/2, scale)      8
+#   -ln u: log2 (2) and two multiplies; mu = 2u - 1 (2)                     6
+#   wall distance and reciprocal, hit test, segment select                 8
+#   position update                                                        2
+#   two bin indices (scale, floor, convert, 2 clamps) and 2 compares       12
+#   three FP64 tally accumulations (5 FP32 products, 3 converts, 3 adds)   11
+#   gain alias draw (shift, mask, compare, select) + state fetch address    6
+#   flight / scatter counters, truncation and cap tests                    5
+# plus 2 for the sign and select logic of the boundary/scatter outcome.
+OPS_PER_FLIGHT = 117
 CU, LANES_PER_CU_CLK, CLOCK = 256, 64, 2.4e9
 PEAK_LANE_OPS = CU * LANES_PER_CU_CLK * CLOCK  # 3.93e13 full-rate VALU lane-ops/s
 
@@ -80,7 +83,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=float, default=1e8, help="particles per film")
-    ap.add_argument("--plain-n", type=float, default=2e5, help="particles per film for the plain-form sample")
+    ap.add_argument("--plain-n", type=float, default=1e6, help="particles per film for the plain-form sample")
+    ap.add_argument("--chunk", type=int, default=4096)
+    ap.add_argument("--refill-min", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
@@ -102,7 +107,8 @@ def main():
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
 
     def step():
-        r = b.simulate(jobs, material=mat, precision="fp32", form="persistent", stream=stream, workspace=ws)
+        r = b.simulate(jobs, material=mat, precision="fp32", form="persistent", stream=stream, workspace=ws,
+                       chunk=args.chunk, refill_min=args.refill_min)
         return r, r.stats(-1)
 
     for i in range(args.warmup):

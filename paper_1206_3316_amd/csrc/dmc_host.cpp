@@ -317,8 +317,8 @@ int device_cus()
 // ----------------------------------------------------------- launch plan ----
 
 dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, const std::vector<double> &times,
-                          const LaunchBuffers &b, size_t tally_doubles, bool zero_tally, const dmc_run_opts &o,
-                          hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+                          std::vector<JobDev> &table, const LaunchBuffers &b, size_t tally_doubles, bool zero_tally,
+                          const dmc_run_opts &o, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     const int n_jobs = (int)devs.size();
     bool slab_only = true;
@@ -390,7 +390,10 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
         a.refill_min = 64;
         lds_bytes = stats_lds;
     }
-    DMC_HIP_OR_FAIL(hipMemcpyAsync(b.jobs, devs.data(), devs.size() * sizeof(JobDev), hipMemcpyHostToDevice, s));
+    // the device table is ordered by queue position (the kernels search it by base)
+    table = devs;
+    std::stable_sort(table.begin(), table.end(), [](const JobDev &x, const JobDev &y) { return x.base < y.base; });
+    DMC_HIP_OR_FAIL(hipMemcpyAsync(b.jobs, table.data(), table.size() * sizeof(JobDev), hipMemcpyHostToDevice, s));
     if (!times.empty())
         DMC_HIP_OR_FAIL(hipMemcpyAsync(b.times, times.data(), times.size() * sizeof(double), hipMemcpyHostToDevice, s));
     DMC_HIP_OR_FAIL(launch_fill(zero_tally ? b.tally : nullptr, zero_tally ? tally_doubles : 0, b.stats,
@@ -455,22 +458,45 @@ Layout layout_of(const std::vector<JobHost> &jh)
     return L;
 }
 
+// Expected flights per particle, used to queue the longest trajectories first:
+// trajectory lengths are heavy-tailed, and the longest single particle bounds
+// a launch's duration unless it starts early.
+double flights_per_particle(const dmc_material &M, const JobHost &h)
+{
+    const JobDev &d = h.dev;
+    if (d.src == SRC_WALLS) return 2.0 * h.geom.length * M.G_tau / M.G_v + 1.0;
+    if (d.src == SRC_GAUSSIAN) return h.times.back() * M.G_tau / M.C_tot + 1.0;
+    return d.kmax >= 0 ? 1.5 * d.kmax + 1.0 : 1000.0;
+}
+
 dmc_status gather_jobs(const dmc_job *jobs, int32_t n_jobs, std::vector<JobHost> &jh)
 {
     if (!jobs || n_jobs < 1 || n_jobs > kMaxJobs) return fail(DMC_E_INVALID, "n_jobs must be 1..4096");
     jh.resize(n_jobs);
     const dmc_material *M = jobs[0].material;
-    uint64_t base = 0;
-    int64_t toff = 0, tim = 0;
     for (int i = 0; i < n_jobs; ++i) {
         if (jobs[i].material != M) return fail(DMC_E_INVALID, "all jobs of a launch must share one material");
         dmc_status st = prepare_job(jobs[i], jh[i]);
         if (st != DMC_OK) return st;
-        JobDev &d = jh[i].dev;
+    }
+    // queue order: descending expected flights per particle (ties: caller's order)
+    std::vector<int> order(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) order[i] = i;
+    std::vector<double> f(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) f[i] = flights_per_particle(*M, jh[i]);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return f[x] > f[y]; });
+    uint64_t base = 0;
+    for (int r = 0; r < n_jobs; ++r) {
+        JobDev &d = jh[order[r]].dev;
         if (base + d.n < base) return fail(DMC_E_INVALID, "particle count overflow");
         d.base = base;
-        d.pid0 = 0;
         base += d.n;
+    }
+    int64_t toff = 0, tim = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        JobDev &d = jh[i].dev;
+        d.pid0 = 0;
+        d.stat_slot = i;
         if (d.off_bins >= 0) d.off_bins += toff;
         if (d.off_kappa >= 0) d.off_kappa += toff;
         if (d.off_hj >= 0) d.off_hj += toff;
@@ -519,14 +545,15 @@ dmc_status launch(std::vector<JobHost> &jh, const dmc_run_opts &o, dmc_result **
     R->d_stats = b.stats;
     R->tally_doubles = L.tally_doubles;
     std::vector<JobDev> devs(jh.size());
-    std::vector<double> times;
+    std::vector<double> &times = R->h_times;
     for (size_t i = 0; i < jh.size(); ++i) {
         devs[i] = jh[i].dev;
         times.insert(times.end(), jh[i].times.begin(), jh[i].times.end());
     }
     HIP_OR_FAIL(hipEventCreate(&R->ev0));
     HIP_OR_FAIL(hipEventCreate(&R->ev1));
-    dmc_status st = enqueue_launch(M, devs, times, b, L.tally_doubles, true, o, R->stream, R->ev0, R->ev1);
+    dmc_status st =
+        enqueue_launch(M, devs, times, R->h_table, b, L.tally_doubles, true, o, R->stream, R->ev0, R->ev1);
     if (st != DMC_OK) {
         (void)hipStreamSynchronize(R->stream);
         return st;

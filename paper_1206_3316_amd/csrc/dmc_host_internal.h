@@ -58,9 +58,11 @@ struct LaunchBuffers {
 // counters (and the tallies if zero_tally), records ev0, enqueues the
 // trajectory launch(es) and records ev1, all on `stream`.  `devs` receives the
 // LDS offsets chosen.
+// `table` receives the host copy of the uploaded descriptor table; it and
+// `times` must stay alive until the launch has completed (asynchronous copies).
 dmc_status enqueue_launch(const struct ::dmc_material *M, std::vector<JobDev> &devs, const std::vector<double> &times,
-                          const LaunchBuffers &b, size_t tally_doubles, bool zero_tally, const dmc_run_opts &o,
-                          hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+                          std::vector<JobDev> &table, const LaunchBuffers &b, size_t tally_doubles, bool zero_tally,
+                          const dmc_run_opts &o, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
 
 }  // namespace dmc
 
@@ -94,6 +96,8 @@ struct dmc_result {
     bool synced = false;
     std::vector<double> h_tally;
     std::vector<unsigned long long> h_stats;
+    std::vector<dmc::JobDev> h_table;  // upload sources, alive until the launch completes
+    std::vector<double> h_times;
     double kernel_ms = 0.0;
     ~dmc_result();
 };

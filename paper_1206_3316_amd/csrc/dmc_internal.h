@@ -48,6 +48,8 @@ struct alignas(16) JobDev {
     int32_t grid[3], pad0;
     double grid_lo[3], grid_ext[3];  // lower bound and extent hi - lo
     int64_t ncell;
+    int32_t stat_slot;      // index of this job's counters (the caller's job index)
+    int32_t pad1;
 };
 
 struct KArgs {

@@ -152,9 +152,10 @@ struct Pr<double> {
 template <>
 struct Pr<float> {
     static constexpr float inf() { return __builtin_huge_valf(); }
-    // ((w >> 8) + 1/2) 2^-24: exact, strictly inside (0, 1)
+    // ((w >> 8) + 1/2) 2^-24: exact, strictly inside (0, 1), never denormal
     __device__ static float u(uint32_t w) { return ((float)(w >> 8) + 0.5f) * 5.9604644775390625e-08f; }
-    __device__ static float flight(float tau, uint32_t w) { return -tau * __logf(u(w)); }
+    // -tau ln u with the hardware log2 (u >= 2^-25, so no range fix-ups are needed)
+    __device__ static float flight(float tau, uint32_t w) { return (tau * -0.693147182f) * __builtin_amdgcn_logf(u(w)); }
     __device__ static float sq(float x) { return __builtin_amdgcn_sqrtf(x); }
     // v_sin / v_cos take revolutions: sin(2 pi u) = sin_rev(u)
     __device__ static void cs(uint32_t w, float &c, float &s)
@@ -163,9 +164,9 @@ struct Pr<float> {
         c = __builtin_amdgcn_cosf(r);
         s = __builtin_amdgcn_sinf(r);
     }
-    __device__ static float div(float a, float b) { return __fdividef(a, b); }
+    __device__ static float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     __device__ static float ptime(float t, float, float itau) { return t * itau; }
-    __device__ static float lg(float x) { return __logf(x); }
+    __device__ static float lg(float x) { return __builtin_amdgcn_logf(x) * 0.693147182f; }
     // a position rounded just past a wall must not yield a negative flight time
     __device__ static float nonneg(float t) { return fmaxf(t, 0.0f); }
 };
@@ -180,11 +181,15 @@ struct Lane {
     int32_t last;           // surface the particle rests on (excluded from the next search)
     uint32_t k, nscat, nbound;
     uint64_t pid, qidx;
-    int32_t job, batch;
+    int32_t job, batch, slot;
     // cached job parameters
     int32_t geom, src, n_bins, n_hj, kmax, n_times;
     R len, bpl, bw;
     uint32_t key0, key1;
+    // tally addresses of this particle: bins of its batch (LDS index or, if
+    // bl < 0, HBM offset) and the H_j block
+    int32_t bl, hl;
+    int64_t bg, hg;
     // accumulators
     double t, Lz, h;
     int32_t cbin;
@@ -226,13 +231,13 @@ __device__ __forceinline__ void gadd(double *p, double v) { atomicAdd(p, v); }
 __device__ __forceinline__ void gaddu(unsigned long long *p, unsigned long long v) { atomicAdd(p, v); }
 
 // Adds to a tally slot that lives in LDS when lds_off >= 0, else in HBM.
-__device__ __forceinline__ void tadd(const KArgs &a, const Shared &sh, int32_t lds_off, int64_t g_off, int64_t idx,
+__device__ __forceinline__ void tadd(const KArgs &a, const Shared &sh, int32_t lds_off, int64_t g_off, int32_t idx,
                                      double v)
 {
     if (lds_off >= 0)
-        atomicAdd(sh.ltally + lds_off + idx, v);
+        atomicAdd(sh.ltally + (lds_off + idx), v);
     else
-        gadd(a.tally + g_off + idx, v);
+        gadd(a.tally + (g_off + idx), v);
 }
 
 // ------------------------------------------------------------ emission ----
@@ -276,6 +281,7 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
     p.pid = pid;
     p.qidx = qidx;
     p.job = job;
+    p.slot = J.stat_slot;
     p.batch = (int32_t)(pid % (uint64_t)J.n_batches);
     p.geom = (G == GEOM_ANY) ? J.geom : G;
     p.src = J.src;
@@ -299,6 +305,13 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
     p.cbin = -1;
     p.c0 = p.c1 = p.c2 = 0.0;
     p.tcur = 0;
+    {
+        const int32_t boff = p.batch * 3 * p.n_bins;
+        p.bl = (J.lds_bins >= 0) ? J.lds_bins + boff : -1;
+        p.bg = J.off_bins + boff;
+        p.hl = J.lds_hj;
+        p.hg = J.off_hj;
+    }
 
     const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
     const uint4 A = philox(plo, phi, 0u, TAG_EMIT_A, p.key0, p.key1);
@@ -365,38 +378,35 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
 // ------------------------------------------------------------- scoring ----
 
 template <typename R, int FORM>
-__device__ __forceinline__ void bin_flush(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J)
+__device__ __forceinline__ void bin_flush(Lane<R> &p, const KArgs &a, const Shared &sh)
 {
     if (p.cbin < 0) return;
-    const int64_t base = ((int64_t)p.batch * 3) * p.n_bins + p.cbin;
-    tadd(a, sh, J.lds_bins, J.off_bins, base, p.c0);
-    tadd(a, sh, J.lds_bins, J.off_bins, base + p.n_bins, p.c1);
-    tadd(a, sh, J.lds_bins, J.off_bins, base + 2 * p.n_bins, p.c2);
+    tadd(a, sh, p.bl, p.bg, p.cbin, p.c0);
+    tadd(a, sh, p.bl, p.bg, p.cbin + p.n_bins, p.c1);
+    tadd(a, sh, p.bl, p.bg, p.cbin + 2 * p.n_bins, p.c2);
     p.cbin = -1;
     p.c0 = p.c1 = p.c2 = 0.0;
 }
 
 // Time t spent in bin k: TIME += s t, PTIME += s t / tau, DISP += s v Omega_z t.
 template <typename R, int FORM>
-__device__ __forceinline__ void bin_add(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, int k, R t,
-                                        R vz, bool cache)
+__device__ __forceinline__ void bin_add(Lane<R> &p, const KArgs &a, const Shared &sh, int k, R t, R vz, bool cache)
 {
     const double d0 = (double)(p.s * t);
     const double d1 = (double)(p.s * Pr<R>::ptime(t, p.tau, p.itau));
     const double d2 = (double)(p.s * vz * t);
     if (FORM == FORM_PERSISTENT && cache) {
         if (k != p.cbin) {
-            bin_flush<R, FORM>(p, a, sh, J);
+            bin_flush<R, FORM>(p, a, sh);
             p.cbin = k;
         }
         p.c0 += d0;
         p.c1 += d1;
         p.c2 += d2;
     } else {
-        const int64_t base = ((int64_t)p.batch * 3) * p.n_bins + k;
-        tadd(a, sh, J.lds_bins, J.off_bins, base, d0);
-        tadd(a, sh, J.lds_bins, J.off_bins, base + p.n_bins, d1);
-        tadd(a, sh, J.lds_bins, J.off_bins, base + 2 * p.n_bins, d2);
+        tadd(a, sh, p.bl, p.bg, k, d0);
+        tadd(a, sh, p.bl, p.bg, k + p.n_bins, d1);
+        tadd(a, sh, p.bl, p.bg, k + 2 * p.n_bins, d2);
     }
 }
 
@@ -418,32 +428,32 @@ __device__ void score_bins(Lane<R> &p, const KArgs &a, const Shared &sh, const J
     const int nb = p.n_bins;
     const int ka = bin_of(ca, p.bpl, nb);
     if (wa == (R)0) {
-        bin_add<R, FORM>(p, a, sh, J, ka, seg, vz, true);
+        bin_add<R, FORM>(p, a, sh, ka, seg, vz, true);
         return;
     }
     const R cb = ca + wa * seg;
     const int kb = bin_of(cb, p.bpl, nb);
     if (ka == kb) {
-        bin_add<R, FORM>(p, a, sh, J, ka, seg, vz, true);
+        bin_add<R, FORM>(p, a, sh, ka, seg, vz, true);
         return;
     }
     const R aw = fabs(wa);
-    const R inv = (R)1 / aw;
+    const R inv = Pr<R>::div((R)1, aw);
     const R bw = p.bw;
     if (wa > (R)0) {
         const R t0 = fmax(((R)(ka + 1) * bw - ca) * inv, (R)0);
-        bin_add<R, FORM>(p, a, sh, J, ka, t0, vz, true);
+        bin_add<R, FORM>(p, a, sh, ka, t0, vz, true);
         const R tin = bw * inv;
-        for (int k = ka + 1; k < kb; ++k) bin_add<R, FORM>(p, a, sh, J, k, tin, vz, false);
+        for (int k = ka + 1; k < kb; ++k) bin_add<R, FORM>(p, a, sh, k, tin, vz, false);
         const R t1 = fmax((cb - (R)kb * bw) * inv, (R)0);
-        bin_add<R, FORM>(p, a, sh, J, kb, t1, vz, true);
+        bin_add<R, FORM>(p, a, sh, kb, t1, vz, true);
     } else {
         const R t0 = fmax((ca - (R)ka * bw) * inv, (R)0);
-        bin_add<R, FORM>(p, a, sh, J, ka, t0, vz, true);
+        bin_add<R, FORM>(p, a, sh, ka, t0, vz, true);
         const R tin = bw * inv;
-        for (int k = ka - 1; k > kb; --k) bin_add<R, FORM>(p, a, sh, J, k, tin, vz, false);
+        for (int k = ka - 1; k > kb; --k) bin_add<R, FORM>(p, a, sh, k, tin, vz, false);
         const R t1 = fmax(((R)(kb + 1) * bw - cb) * inv, (R)0);
-        bin_add<R, FORM>(p, a, sh, J, kb, t1, vz, true);
+        bin_add<R, FORM>(p, a, sh, kb, t1, vz, true);
     }
 }
 
@@ -488,21 +498,20 @@ __device__ __forceinline__ R search(const Lane<R> &p, const JobDev &J, int geom,
     R best = Pr<R>::inf();
     surf = kNoSurface;
     if (geom == GEOM_SLAB || geom == GEOM_FILM) {
+        // one candidate plane, chosen by the sign of the axial speed; one division
         const R c = (geom == GEOM_SLAB) ? p.z : p.x;
         const R w = p.v * ((geom == GEOM_SLAB) ? p.oz : p.ox);
-        if (w > (R)0 && p.last != 1) {
-            best = Pr<R>::div(p.len - c, w);
-            surf = 1;
-        } else if (w < (R)0 && p.last != 0) {
-            best = Pr<R>::div((R)0 - c, w);
-            surf = 0;
-        }
+        const bool up = w > (R)0;
+        const int32_t cand = up ? 1 : 0;
+        const bool ok = (up || w < (R)0) && p.last != cand;
+        const R dist = up ? (p.len - c) : ((R)0 - c);
+        best = ok ? Pr<R>::div(dist, w) : best;
+        surf = ok ? cand : kNoSurface;
     } else if (geom == GEOM_HALF) {
         const R w = p.v * p.oz;
-        if (w < (R)0 && p.last != 0) {
-            best = Pr<R>::div((R)0 - p.z, w);
-            surf = 0;
-        }
+        const bool ok = w < (R)0 && p.last != 0;
+        best = ok ? Pr<R>::div((R)0 - p.z, w) : best;
+        surf = ok ? 0 : kNoSurface;
     } else {  // pore cell: faces 0: x=0, 1: x=P, 2: z=0, 3: z=P, 4: pore surface
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
@@ -613,25 +622,25 @@ __device__ bool interact(Lane<R> &p, const JobDev &J, int32_t surf, const uint4 
 template <typename R, int FORM>
 __device__ void finish(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, bool capped)
 {
-    if (p.n_bins > 0) bin_flush<R, FORM>(p, a, sh, J);
+    if (p.n_bins > 0) bin_flush<R, FORM>(p, a, sh);
     if (J.off_kappa >= 0) {
         tadd(a, sh, J.lds_kappa, J.off_kappa, 0, p.Lz);
         tadd(a, sh, J.lds_kappa, J.off_kappa, 1, p.Lz * p.Lz);
     }
     if (p.n_hj > 0 && p.nscat < (uint32_t)p.n_hj) {
-        tadd(a, sh, J.lds_hj, J.off_hj, p.nscat, p.h);
-        tadd(a, sh, J.lds_hj, J.off_hj, p.n_hj + p.nscat, p.h * p.h);
+        tadd(a, sh, p.hl, p.hg, (int32_t)p.nscat, p.h);
+        tadd(a, sh, p.hl, p.hg, p.n_hj + (int32_t)p.nscat, p.h * p.h);
     }
     if (a.nscat_out) a.nscat_out[p.qidx] = p.nscat;
     const unsigned long long vals[kStats] = {1ull, p.nscat, p.nbound, p.k, capped ? 1ull : 0ull};
     if (a.lds_stats) {
 #pragma unroll
         for (int i = 0; i < kStats; ++i)
-            if (vals[i]) atomicAdd(sh.lstats + p.job * kStats + i, vals[i]);
+            if (vals[i]) atomicAdd(sh.lstats + p.slot * kStats + i, vals[i]);
     } else {
 #pragma unroll
         for (int i = 0; i < kStats; ++i)
-            if (vals[i]) gaddu(a.stats + (int64_t)p.job * kStats + i, vals[i]);
+            if (vals[i]) gaddu(a.stats + (int64_t)p.slot * kStats + i, vals[i]);
     }
 }
 
@@ -687,8 +696,8 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
         isotropic(p, w.z, w.w);
         p.last = kNoSurface;
         if (gradient && p.nscat < (uint32_t)p.n_hj) {
-            tadd(a, sh, J.lds_hj, J.off_hj, p.nscat, p.h);
-            tadd(a, sh, J.lds_hj, J.off_hj, p.n_hj + p.nscat, p.h * p.h);
+            tadd(a, sh, p.hl, p.hg, (int32_t)p.nscat, p.h);
+            tadd(a, sh, p.hl, p.hg, p.n_hj + (int32_t)p.nscat, p.h * p.h);
             p.h = 0.0;
         }
         ++p.nscat;

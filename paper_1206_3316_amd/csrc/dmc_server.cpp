@@ -98,6 +98,8 @@ struct dmc_server {
     std::vector<std::unique_ptr<Request>> active;
     std::map<uint64_t, std::unique_ptr<Request>> done;
     uint64_t next_ticket = 1;
+    std::vector<JobDev> epoch_table;  // upload sources of the running epoch
+    std::vector<double> epoch_times;
     ~dmc_server()
     {
         if (ev0) (void)hipEventDestroy(ev0);
@@ -188,7 +190,8 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
     if (n_done) *n_done = 0;
     hipStream_t s = (hipStream_t)S->opts.run.stream;
     std::vector<JobDev> devs;
-    std::vector<double> times;
+    std::vector<double> &times = S->epoch_times;
+    times.clear();
     std::vector<Request *> members;
     {
         std::lock_guard<std::mutex> g(S->mu);
@@ -221,6 +224,7 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
             d.base = base;
             d.n = n;
             d.pid0 = r->cursor;
+            d.stat_slot = (int32_t)devs.size();
             d.times_off = (int32_t)times.size();
             times.insert(times.end(), r->jh.times.begin(), r->jh.times.end());
             base += n;
@@ -228,7 +232,7 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
             members.push_back(r);
         }
     }
-    dmc_status st = enqueue_launch(S->M, devs, times, S->sb, 0, false, S->opts.run, s, S->ev0, S->ev1);
+    dmc_status st = enqueue_launch(S->M, devs, times, S->epoch_table, S->sb, 0, false, S->opts.run, s, S->ev0, S->ev1);
     if (st != DMC_OK) return st;
     DMC_HIP_OR_FAIL(hipEventSynchronize(S->ev1));
     float ms = 0.0f;
