@@ -20,6 +20,7 @@ bounded sample on the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -45,6 +46,11 @@ sys.path.insert(0, ROOT)
 #   flight / scatter counters, truncation and cap tests                    5
 # plus 2 for the sign and select logic of the boundary/scatter outcome.
 OPS_PER_FLIGHT = 117
+# HBM traffic of one launch of the timed workload from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs (profiles/), scaled by the same counters' reading for a plain
+# device copy of known size (bench.py --copy-probe); valid only for the kernel
+# source it was measured on.
+TRAFFIC = {"kernel_sha1": "7f61830f418821ca350fc7a39e81ae3b689132c6", "bytes": 33842586}  # profiles/persistent_kernel_slab_12films_counters.md
 CU, LANES_PER_CU_CLK, CLOCK = 256, 64, 2.4e9
 PEAK_LANE_OPS = CU * LANES_PER_CU_CLK * CLOCK  # 3.93e13 full-rate VALU lane-ops/s
 
@@ -54,13 +60,13 @@ def log(msg):
 
 
 def cpu_baseline(jobs, target_s=15.0):
-    """The FP64 oracle on a bounded sample of every film, all host cores."""
+    """The FP64 oracle on a bounded sample of every film, on the host cores."""
     import oracle
 
     threads = os.cpu_count() or 1
     if "OMP_NUM_THREADS" in os.environ:
         threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
-    # calibrate on a small sample, then size the sample to ~target_s
+
     def run(n):
         ev = 0
         t0 = time.perf_counter()
@@ -69,12 +75,105 @@ def cpu_baseline(jobs, target_s=15.0):
             ev += cnt["scatters"]
         return ev, time.perf_counter() - t0
 
-    ev, dt = run(64)
-    n = max(64, int(64 * target_s / max(dt, 1e-3)))
-    n = min(n, 200_000)
+    n = 256
     ev, dt = run(n)
+    # heavy-tailed trajectory lengths make small samples noisy: grow until the
+    # sample itself takes at least a third of the target
+    while dt < target_s / 3 and n < 4_000_000:
+        n = int(n * min(8.0, max(2.0, target_s / max(dt, 1e-3))))
+        ev, dt = run(n)
     return {"value": ev / dt, "unit": "scattering events/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} particles of each of the 12 films ({ev} scattering events, {dt:.1f} s)"}
+
+
+def flights_per_particle(job, sums):
+    C_tot, G_tau, G_v = sums
+    if job.source.kind == "walls":
+        return 2.0 * job.geometry.length * G_tau / G_v + 1.0
+    if job.source.kind == "gaussian":
+        return job.tally.times[-1] * G_tau / C_tot + 1.0
+    return 1.5 * job.tally.kmax + 1.0
+
+
+def serve(b, di, torch, mat, mat_in, stream, capacity, n_requests, args):
+    """Poisson stream of mixed requests (films, heated spots, pore cells) on the
+    continuous-batching server at 0.8 x measured capacity; p50/p99 latency."""
+    _, sums = mat.info()
+    reqs = di.serving_stream(n_requests, material=mat_in)
+    work = [j.n_particles * flights_per_particle(j, sums) for _, j in reqs]
+    rate = 0.8 * capacity / (sum(work) / len(work))
+    arrivals = di.poisson_arrivals(n_requests, rate)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(0.8 * free, 64 << 30))
+    srv = b.Server(mat, budget, max_active=32, epoch_flights=args.epoch_flights, stream=stream,
+                   chunk=args.chunk, refill_min=args.refill_min)
+    lat, kinds, scat = [], [], 0
+    pending = {}
+    i = 0
+    epochs = 0
+    epoch_s = 0.0
+    t0 = time.perf_counter()
+    last_log = 0.0
+    while len(lat) < i or i < n_requests:
+        now = time.perf_counter() - t0
+        if now > args.serve_max_s and i < n_requests:
+            log(f"serving: stopping arrivals after {now:.0f} s ({i} of {n_requests} requests submitted)")
+            n_requests = i
+            continue
+        while i < n_requests and arrivals[i] <= now:
+            pending[srv.submit(reqs[i][1])] = (i, arrivals[i])
+            i += 1
+        q, r = srv.load()
+        if q + r > 0:
+            te = time.perf_counter()
+            srv.step()
+            epochs += 1
+            epoch_s += time.perf_counter() - te
+            t_done = time.perf_counter() - t0
+            for t in [t for t in pending if srv.done(t)]:
+                k, ta = pending.pop(t)
+                res = srv.collect(t)
+                scat += res.stats(0).scatters
+                lat.append(t_done - ta)
+                kinds.append(reqs[k][0])
+                if k < 2:  # the same request alone must give the same result
+                    solo = b.simulate([reqs[k][1]], material=mat, stream=stream, chunk=args.chunk)
+                    a, c = res.raw(0), solo.raw(0)
+                    d = float(abs(a - c).max() / max(abs(c).max(), 1e-300))
+                    serve.mix_vs_alone = max(getattr(serve, "mix_vs_alone", 0.0), d)
+                res.close()
+        elif i < n_requests:
+            time.sleep(max(0.0, min(arrivals[i] - now, 0.05)))
+        if time.perf_counter() - t0 - last_log > 5.0:
+            last_log = time.perf_counter() - t0
+            log(f"serving t={last_log:.0f}s submitted {i} done {len(lat)} queued {q} running {r} "
+                f"epochs {epochs} mean epoch {1e3 * epoch_s / max(epochs, 1):.1f} ms "
+                f"events/s {scat / max(last_log, 1e-9):.3e}")
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat_s = sorted(lat)
+    pct = lambda p: lat_s[min(len(lat_s) - 1, int(round(p / 100.0 * (len(lat_s) - 1))))]
+    return {"requests": n_requests, "arrival_rate_per_s": rate, "p50_latency_s": pct(50), "p99_latency_s": pct(99),
+            "scattering_events_per_s": scat / wall, "wall_s": wall, "epochs": epochs,
+            "mean_epoch_ms": 1e3 * epoch_s / max(epochs, 1),
+            "mix_vs_alone_max_rel_diff": getattr(serve, "mix_vs_alone", None),
+            "mix": {k: kinds.count(k) for k in sorted(set(kinds))}}
+
+
+def copy_probe():
+    """A plain device copy of known size, for scaling the HBM traffic counters."""
+    import torch
+    n = 1 << 30
+    x = torch.empty(n, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n}))
+
+
+def kernel_sha1():
+    p = os.path.join(ROOT, "paper_1206_3316_amd", "csrc", "dmc_kernels.hip")
+    return hashlib.sha1(open(p, "rb").read()).hexdigest()
 
 
 def main():
@@ -88,7 +187,14 @@ def main():
     ap.add_argument("--refill-min", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--epoch-flights", type=float, default=2e10)
+    ap.add_argument("--serve-max-s", type=float, default=90.0, help="stop admitting requests after this long")
+    ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md"}))
         sys.exit(2)
@@ -140,7 +246,8 @@ def main():
                    "particles_per_step": parts // args.steps},
         "particles_per_s": parts / wall,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
+                     "traffic": TRAFFIC["bytes"] if TRAFFIC["kernel_sha1"] == kernel_sha1() else None,
                      "kernel": "persistent_kernel<float, GEOM_SLAB>", "ops_per_flight": OPS_PER_FLIGHT,
                      "kernel_ms_per_step": kernel_s * 1e3 / args.steps},
     }
@@ -155,6 +262,10 @@ def main():
                              "kernel_ms": sp.kernel_ms,
                              "persistent_same_sample_events_per_s": sq.scatters / (sq.kernel_ms / 1e3)}
         out["vs_plain"] = value / plain_rate
+    if args.serve_requests > 0:
+        out["serving"] = serve(b, di, torch, mat, mat_in, stream, value, args.serve_requests, args)
+        out["p50_latency_s"] = out["serving"]["p50_latency_s"]
+        out["p99_latency_s"] = out["serving"]["p99_latency_s"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(jobs)
     print(json.dumps(out))

@@ -243,14 +243,19 @@ typedef struct {
     int32_t max_active;    /* requests resident at once (1..64) */
     uint64_t epoch_flights; /* estimated flights per epoch launch, shared equally by the admitted
                                requests (0 = 2e10) */
+    uint32_t drain_flights; /* flights a wave may still run once the epoch's queue is empty before
+                               it suspends its live particles to the next epoch (0 = 2048) */
     dmc_run_opts run;      /* precision / form / stream / parameters of every epoch */
 } dmc_server_opts;
 
 /* The server admits requests while their device memory fits the budget and
  * a slot is free; each epoch is one persistent launch over a slice of every
  * admitted request's particle range, so requests that arrive while others
- * run join at the next epoch.  A request's tallies stay on the device until
- * it is collected. */
+ * run join at the next epoch.  Epochs are time-bounded: particles still in
+ * flight when an epoch drains are suspended on the device and resumed first
+ * in the next epoch with the same random-number counters, so results do not
+ * depend on the slicing.  A request's tallies stay on the device until it
+ * completes; collecting it copies them to the host. */
 dmc_status dmc_server_create(const dmc_material *material, const dmc_server_opts *opts, dmc_server **out);
 /* Queues a request (copied); *ticket identifies it.  DMC_E_INVALID if it can never fit. */
 dmc_status dmc_server_submit(dmc_server *s, const dmc_job *job, uint64_t *ticket);

@@ -72,7 +72,7 @@ class dmc_stats(C.Structure):
 
 class dmc_server_opts(C.Structure):
     _fields_ = [("memory_budget", C.c_size_t), ("max_active", C.c_int32), ("epoch_flights", C.c_uint64),
-                ("run", dmc_run_opts)]
+                ("drain_flights", C.c_uint32), ("run", dmc_run_opts)]
 
 
 _SIGS = {
@@ -472,3 +472,62 @@ def debug_philox(seed: int, pid, k, tag) -> np.ndarray:
     dmc_debug_philox(int(seed), _ptr(pid, C.c_uint64), _ptr(k, C.c_uint32), _ptr(tag, C.c_uint32),
                      _ptr(out, C.c_uint32), n)
     return out
+
+
+class Server:
+    """Continuous-batching server (dmc_server_*): requests share persistent epoch launches."""
+
+    def __init__(self, material: Material, memory_budget: int, max_active: int = 32, epoch_flights: float = 2e10,
+                 drain_flights: int = 0, precision="fp32", stream=None, **params):
+        o = dmc_server_opts()
+        o.memory_budget = int(memory_budget)
+        o.max_active = int(max_active)
+        o.epoch_flights = int(epoch_flights)
+        o.drain_flights = int(drain_flights)
+        o.run = run_opts(precision, "persistent", getattr(stream, "cuda_stream", stream), **params)
+        h = C.c_void_p()
+        dmc_server_create(material.handle, C.byref(o), C.byref(h))
+        self.handle = h
+        self.material = material
+        self._keep = {}
+
+    def submit(self, job) -> int:
+        keep: list = []
+        j = job_struct(job, self.material, keep)
+        t = C.c_uint64()
+        dmc_server_submit(self.handle, C.byref(j), C.byref(t))
+        self._keep[t.value] = (job, keep)
+        return int(t.value)
+
+    def step(self) -> int:
+        n = C.c_int32()
+        dmc_server_step(self.handle, C.byref(n))
+        return int(n.value)
+
+    def done(self, ticket: int) -> bool:
+        d = C.c_int32()
+        dmc_server_poll(self.handle, ticket, C.byref(d))
+        return bool(d.value)
+
+    def collect(self, ticket: int) -> Result:
+        h = C.c_void_p()
+        dmc_server_collect(self.handle, ticket, C.byref(h))
+        job, keep = self._keep.pop(ticket)
+        return Result(h, [job], keep)
+
+    def load(self):
+        q, r = C.c_int32(), C.c_int32()
+        dmc_server_load(self.handle, C.byref(q), C.byref(r))
+        return int(q.value), int(r.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            dmc_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None) and _lib is not None:
+                _lib.dmc_server_destroy(self.handle)
+        except Exception:
+            pass

@@ -346,6 +346,16 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
     a.stats = b.stats;
     a.kpad = 1 << M->gain.bits;
     a.lds_stats = (n_jobs <= kLdsStatJobs) ? 1 : 0;
+    a.drain_iters = b.drain_iters;
+    a.n_resume = b.n_resume;
+    a.resume_in = b.resume_in;
+    a.resume_job = b.resume_job;
+    a.suspend_out = b.suspend_out;
+    a.suspend_cap = b.suspend_cap;
+    a.total += b.n_resume;
+    if ((b.drain_iters || b.n_resume) && o.form != DMC_FORM_PERSISTENT)
+        return fail(DMC_E_INVALID, "time-bounded launches need the persistent form");
+    if (b.n_resume && !b.drain_iters) return fail(DMC_E_INVALID, "resuming needs a time-bounded launch");
     const size_t stats_lds = a.lds_stats ? (size_t)n_jobs * kStats * 8 : 0;
     for (auto &d : devs) d.lds_bins = d.lds_kappa = d.lds_hj = -1;
     int block = 256, grid = 1;
@@ -382,8 +392,18 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
         a.chunk = o.chunk > 0 ? o.chunk : 1024;
         a.refill_min = o.refill_min > 0 ? o.refill_min : 16;
         block = o.block > 0 ? o.block : (lds_bytes > 64 * 1024 ? 1024 : 512);
-        const int per_cu = occupancy_blocks(o.precision, o.form, slab_only, block, lds_bytes);
+        const bool bounded = b.drain_iters > 0 || b.n_resume > 0;
+        const int per_cu = occupancy_blocks(o.precision, o.form, slab_only && !bounded, bounded, block, lds_bytes);
         grid = o.grid_blocks > 0 ? o.grid_blocks : device_cus() * per_cu;
+        if (b.drain_iters) {
+            // every lane may suspend one particle and every wave the unstarted rest of
+            // its chunk: chunks are capped at one index per lane
+            a.chunk = std::min(a.chunk, 64);
+            const uint32_t per_block = (uint32_t)block + (uint32_t)(block / 64) * (uint32_t)a.chunk;
+            const int max_grid = (int)(b.suspend_cap / per_block);
+            if (max_grid < 1) return fail(DMC_E_INVALID, "suspend buffer smaller than one workgroup");
+            grid = std::min(grid, max_grid);
+        }
     } else {
         a.lds_tally_doubles = 0;
         a.chunk = 0;

@@ -52,6 +52,13 @@ struct LaunchBuffers {
     double *tally = nullptr;          // tally base (job offsets are relative to it)
     unsigned long long *stats = nullptr;  // n_jobs * kStats counters
     unsigned long long *queue = nullptr;  // 2 words
+    // time-bounded launches (server epochs)
+    uint32_t drain_iters = 0;
+    uint32_t n_resume = 0;
+    const Suspended *resume_in = nullptr;
+    const int32_t *resume_job = nullptr;
+    Suspended *suspend_out = nullptr;
+    uint32_t suspend_cap = 0;
 };
 
 // Plans LDS privatisation and occupancy, uploads the descriptors, clears the

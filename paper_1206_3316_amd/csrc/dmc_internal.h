@@ -14,7 +14,7 @@ constexpr int kMaxBins = 4096;
 constexpr int kMaxTimes = 1024;
 constexpr int kMaxHj = 1024;
 constexpr int kLdsStatJobs = 64;         // per-job counters privatised in LDS up to this many jobs
-constexpr int kStats = 5;                // particles, scatters, boundary, iterations, capped
+constexpr int kStats = 6;                // particles, scatters, boundary, iterations, capped, suspended
 
 enum Geom : int32_t { GEOM_SLAB = 0, GEOM_FILM = 1, GEOM_PORE = 2, GEOM_HALF = 3, GEOM_ANY = 9 };
 enum Wall : int32_t { WALL_ISOTHERMAL = 0, WALL_ADIABATIC = 1, WALL_PERIODIC = 2 };
@@ -52,6 +52,16 @@ struct alignas(16) JobDev {
     int32_t pad1;
 };
 
+// A particle suspended at the end of a time-bounded launch (serving epochs):
+// everything needed to continue its trajectory bit for bit in a later launch.
+struct alignas(16) Suspended {
+    double x, y, z, ox, oy, oz;
+    double t, Lz, h;
+    uint64_t pid;
+    uint32_t k, nscat, nbound, m;
+    int32_t last, tcur, slot, sign;
+};
+
 struct KArgs {
     const JobDev *jobs;
     int32_t n_jobs;
@@ -71,6 +81,15 @@ struct KArgs {
     int32_t lds_tally_doubles;      // LDS tally size; 0 = none
     int32_t lds_stats;              // 1: per-job counters in LDS
     int32_t kpad;                   // 2^gain_bits
+    // time-bounded launches (persistent form): queue indices [0, n_resume) resume
+    // suspended particles; a wave that finds the queue empty runs at most
+    // drain_iters more flights, then suspends its live particles
+    uint32_t drain_iters;           // 0: run every particle to completion
+    uint32_t n_resume;
+    const Suspended *resume_in;
+    const int32_t *resume_job;      // device-table job of each resumed particle's slot
+    Suspended *suspend_out;
+    uint32_t suspend_cap;
 };
 
 // Packed alias entry: column idx of a table with b index bits keeps idx iff
@@ -95,6 +114,6 @@ hipError_t launch_debug_alias(const uint32_t *packed, int bits, const uint32_t *
                               hipStream_t stream);
 hipError_t launch_debug_math(const double *x, double *lg, double *sn, double *cs, size_t n, hipStream_t stream);
 int max_lds_bytes();
-int occupancy_blocks(int precision, int form, bool slab_only, int block, size_t lds_bytes);
+int occupancy_blocks(int precision, int form, bool slab_only, bool bounded, int block, size_t lds_bytes);
 
 }  // namespace dmc

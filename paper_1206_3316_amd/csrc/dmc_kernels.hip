@@ -177,6 +177,7 @@ template <typename R>
 struct Lane {
     R x, y, z, ox, oy, oz;  // position and unit direction
     R v, tau, itau;         // group speed, relaxation time, 1/tau of the current state
+    uint32_t m;             // state index
     R s;                    // sign
     int32_t last;           // surface the particle rests on (excluded from the next search)
     uint32_t k, nscat, nbound;
@@ -210,6 +211,7 @@ __device__ __forceinline__ void load_state(Lane<R> &p, const KArgs &a, const Sha
 template <>
 __device__ __forceinline__ void load_state<float>(Lane<float> &p, const KArgs &a, const Shared &sh, uint32_t m)
 {
+    p.m = m;
     const float4 q = reinterpret_cast<const float4 *>(sh.st)[m];
     p.v = q.x;
     p.tau = q.y;
@@ -219,6 +221,7 @@ __device__ __forceinline__ void load_state<float>(Lane<float> &p, const KArgs &a
 template <>
 __device__ __forceinline__ void load_state<double>(Lane<double> &p, const KArgs &a, const Shared &sh, uint32_t m)
 {
+    p.m = m;
     const double2 q = reinterpret_cast<const double2 *>(sh.st)[m];
     p.v = q.x;
     p.tau = q.y;
@@ -274,12 +277,11 @@ __device__ __forceinline__ void isotropic(Lane<R> &p, uint32_t w2, uint32_t w3)
     p.oz = mu;
 }
 
+// Per-particle copies of its job's parameters.
 template <typename R, int G>
-__device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, uint64_t qidx, int job)
+__device__ __forceinline__ void bind_job(Lane<R> &p, const JobDev &J, uint64_t pid, int job)
 {
-    const uint64_t pid = J.pid0 + (qidx - J.base);
     p.pid = pid;
-    p.qidx = qidx;
     p.job = job;
     p.slot = J.stat_slot;
     p.batch = (int32_t)(pid % (uint64_t)J.n_batches);
@@ -294,6 +296,23 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
     p.bw = (R)J.bin_width;
     p.key0 = J.key0;
     p.key1 = J.key1;
+    {
+        const int32_t boff = p.batch * 3 * p.n_bins;
+        p.bl = (J.lds_bins >= 0) ? J.lds_bins + boff : -1;
+        p.bg = J.off_bins + boff;
+        p.hl = J.lds_hj;
+        p.hg = J.off_hj;
+    }
+    p.cbin = -1;
+    p.c0 = p.c1 = p.c2 = 0.0;
+}
+
+template <typename R, int G>
+__device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, uint64_t qidx, int job)
+{
+    const uint64_t pid = J.pid0 + (qidx - J.base - (uint64_t)a.n_resume);
+    bind_job<R, G>(p, J, pid, job);
+    p.qidx = qidx;
     p.x = p.y = p.z = (R)0;
     p.last = kNoSurface;
     p.k = 0;
@@ -302,16 +321,7 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
     p.t = 0.0;
     p.Lz = 0.0;
     p.h = 0.0;
-    p.cbin = -1;
-    p.c0 = p.c1 = p.c2 = 0.0;
     p.tcur = 0;
-    {
-        const int32_t boff = p.batch * 3 * p.n_bins;
-        p.bl = (J.lds_bins >= 0) ? J.lds_bins + boff : -1;
-        p.bg = J.off_bins + boff;
-        p.hl = J.lds_hj;
-        p.hg = J.off_hj;
-    }
 
     const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
     const uint4 A = philox(plo, phi, 0u, TAG_EMIT_A, p.key0, p.key1);
@@ -617,6 +627,64 @@ __device__ bool interact(Lane<R> &p, const JobDev &J, int32_t surf, const uint4 
     return false;
 }
 
+// ------------------------------------------------------- suspend / resume ----
+
+template <typename R, int FORM>
+__device__ void suspend(Lane<R> &p, const KArgs &a, const Shared &sh)
+{
+    if (p.n_bins > 0) bin_flush<R, FORM>(p, a, sh);
+    const uint32_t slot = atomicAdd(reinterpret_cast<unsigned int *>(a.queue + 1), 1u);
+    Suspended &S = a.suspend_out[slot];  // the host sizes the buffer for every lane of the grid
+    S.x = (double)p.x;
+    S.y = (double)p.y;
+    S.z = (double)p.z;
+    S.ox = (double)p.ox;
+    S.oy = (double)p.oy;
+    S.oz = (double)p.oz;
+    S.t = p.t;
+    S.Lz = p.Lz;
+    S.h = p.h;
+    S.pid = p.pid;
+    S.k = p.k;
+    S.nscat = p.nscat;
+    S.nbound = p.nbound;
+    S.m = p.m;
+    S.last = p.last;
+    S.tcur = p.tcur;
+    S.slot = p.slot;
+    S.sign = p.s > (R)0 ? 1 : -1;
+    if (a.lds_stats)
+        atomicAdd(sh.lstats + p.slot * kStats + 5, 1ull);
+    else
+        gaddu(a.stats + (int64_t)p.slot * kStats + 5, 1ull);
+}
+
+template <typename R, int G>
+__device__ void resume(Lane<R> &p, const KArgs &a, const Shared &sh, uint32_t i)
+{
+    const Suspended &S = a.resume_in[i];
+    const int job = a.resume_job[S.slot];
+    const JobDev &J = a.jobs[job];
+    bind_job<R, G>(p, J, S.pid, job);
+    p.qidx = J.base + (uint64_t)a.n_resume + (S.pid - J.pid0);  // only used for nscat_out, which the server does not set
+    p.x = (R)S.x;
+    p.y = (R)S.y;
+    p.z = (R)S.z;
+    p.ox = (R)S.ox;
+    p.oy = (R)S.oy;
+    p.oz = (R)S.oz;
+    p.t = S.t;
+    p.Lz = S.Lz;
+    p.h = S.h;
+    p.k = S.k;
+    p.nscat = S.nscat;
+    p.nbound = S.nbound;
+    p.last = S.last;
+    p.tcur = S.tcur;
+    p.s = (R)S.sign;
+    load_state(p, a, sh, S.m);
+}
+
 // ---------------------------------------------------------------- finish ----
 
 template <typename R, int FORM>
@@ -820,7 +888,9 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
     return ((uint64_t)hi << 32) | lo;
 }
 
-template <typename R, int G>
+// BOUNDED: time-bounded launch (serving epochs): resumes suspended particles
+// and suspends the live ones a fixed number of flights after the queue runs dry.
+template <typename R, int G, bool BOUNDED>
 __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -830,20 +900,24 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
     bool alive = false;
     int job = 0;
     uint64_t pool_cur = 0, pool_end = 0;  // wave-uniform slice of the queue
-    bool exhausted = false;
+    bool qdry = false;  // the global queue has handed out every index (wave-uniform)
+    uint32_t drain = 0, poll = 0;
     for (;;) {
-        // refill free lanes from the queue (one atomic per wave per chunk)
+        // refill free lanes from this wave's chunk, taking a new chunk from the
+        // queue (one atomic per wave) when it is used up
         uint64_t need = __ballot(!alive);
         const int n_free = __popcll(need);
-        if (n_free > 0 && !exhausted && (n_free >= a.refill_min || n_free == 64)) {
+        const bool have_work = (pool_cur < pool_end) || !qdry;
+        if (n_free > 0 && have_work && (n_free >= a.refill_min || n_free == 64)) {
             while (need) {
                 if (pool_cur >= pool_end) {
+                    if (qdry) break;
                     const int leader = __ffsll((unsigned long long)need) - 1;
                     uint64_t b = 0;
                     if (lane == leader) b = atomicAdd(a.queue, (unsigned long long)a.chunk);
                     b = shfl64(b, leader);
                     if (b >= a.total) {
-                        exhausted = true;
+                        qdry = true;
                         break;
                     }
                     pool_cur = b;
@@ -857,17 +931,52 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                 const bool mine = ((need >> lane) & 1ull) && (int)below < take;
                 if (mine) {
                     const uint64_t q = pool_cur + below;
-                    job = find_job(a, q, job);
-                    emit<R, G>(p, a, sh, a.jobs[job], q, job);
+                    if (BOUNDED && q < (uint64_t)a.n_resume) {
+                        resume<R, G>(p, a, sh, (uint32_t)q);
+                    } else {
+                        const uint64_t qn = BOUNDED ? q - (uint64_t)a.n_resume : q;
+                        job = find_job(a, qn, job);
+                        emit<R, G>(p, a, sh, a.jobs[job], q, job);
+                    }
                     alive = true;
                 }
                 pool_cur += (uint64_t)take;
                 need &= ~__ballot(mine);
             }
         }
-        if (__ballot(alive) == 0ull) break;
+        if (BOUNDED && !qdry && ((++poll) & 63u) == 0u) {
+            // waves whose lanes are all busy also learn when the queue ran dry
+            const unsigned long long head = __hip_atomic_load(a.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (head >= a.total) qdry = true;
+        }
+        if (__ballot(alive) == 0ull && !((pool_cur < pool_end) || !qdry)) break;
+        if (BOUNDED && qdry) {
+            // time-bounded launch: the queue is dry; a fixed number of flights later
+            // this wave hands its live particles, and any indices of its chunk not yet
+            // started, to the next launch
+            if (++drain > a.drain_iters) {
+                if (alive) suspend<R, FORM_PERSISTENT>(p, a, sh);
+                alive = false;
+                while (pool_cur < pool_end) {
+                    const uint64_t avail = pool_end - pool_cur;
+                    const bool mine = (uint64_t)lane < avail;
+                    if (mine) {
+                        const uint64_t q = pool_cur + (uint64_t)lane;
+                        if (q < (uint64_t)a.n_resume) {
+                            resume<R, G>(p, a, sh, (uint32_t)q);
+                        } else {
+                            job = find_job(a, q - (uint64_t)a.n_resume, job);
+                            emit<R, G>(p, a, sh, a.jobs[job], q, job);
+                        }
+                        suspend<R, FORM_PERSISTENT>(p, a, sh);
+                    }
+                    pool_cur += (avail < 64u) ? avail : 64u;
+                }
+                break;
+            }
+        }
         if (alive) {
-            const JobDev &J = a.jobs[job];
+            const JobDev &J = a.jobs[p.job];
             const int r = step<R, FORM_PERSISTENT, G>(p, a, sh, J);
             if (r != 0) {
                 finish<R, FORM_PERSISTENT>(p, a, sh, J, r == 2);
@@ -930,15 +1039,17 @@ hipError_t launch_debug_math(const double *x, double *lg, double *sn, double *cs
 namespace {
 
 template <typename R, int G>
-const void *kernel_ptr(int form)
+const void *kernel_ptr(int form, bool bounded)
 {
-    return form == FORM_PLAIN ? (const void *)plain_kernel<R, G> : (const void *)persistent_kernel<R, G>;
+    if (form == FORM_PLAIN) return (const void *)plain_kernel<R, G>;
+    return bounded ? (const void *)persistent_kernel<R, GEOM_ANY, true> : (const void *)persistent_kernel<R, G, false>;
 }
 
-const void *pick_kernel(int precision, int form, bool slab_only)
+const void *pick_kernel(int precision, int form, bool slab_only, bool bounded)
 {
-    if (precision == 0) return slab_only ? kernel_ptr<double, GEOM_SLAB>(form) : kernel_ptr<double, GEOM_ANY>(form);
-    return slab_only ? kernel_ptr<float, GEOM_SLAB>(form) : kernel_ptr<float, GEOM_ANY>(form);
+    if (precision == 0)
+        return slab_only ? kernel_ptr<double, GEOM_SLAB>(form, bounded) : kernel_ptr<double, GEOM_ANY>(form, bounded);
+    return slab_only ? kernel_ptr<float, GEOM_SLAB>(form, bounded) : kernel_ptr<float, GEOM_ANY>(form, bounded);
 }
 
 }  // namespace
@@ -946,7 +1057,7 @@ const void *pick_kernel(int precision, int form, bool slab_only)
 hipError_t launch_trajectories(const KArgs &a, int precision, int form, bool slab_only, int block, int grid,
                                size_t lds_bytes, hipStream_t stream)
 {
-    const void *f = pick_kernel(precision, form, slab_only);
+    const void *f = pick_kernel(precision, form, slab_only, a.drain_iters > 0 || a.n_resume > 0);
     if (lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
@@ -986,9 +1097,9 @@ hipError_t launch_debug_alias(const uint32_t *packed, int bits, const uint32_t *
 
 int max_lds_bytes() { return 160 * 1024; }
 
-int occupancy_blocks(int precision, int form, bool slab_only, int block, size_t lds_bytes)
+int occupancy_blocks(int precision, int form, bool slab_only, bool bounded, int block, size_t lds_bytes)
 {
-    const void *f = pick_kernel(precision, form, slab_only);
+    const void *f = pick_kernel(precision, form, slab_only, bounded);
     if (lds_bytes > 64 * 1024) {
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess) {
             (void)hipGetLastError();

@@ -76,9 +76,10 @@ struct Request {
     uint64_t ticket = 0;
     JobHost jh;
     size_t bytes = 0, arena_off = 0;
-    uint64_t cursor = 0;
+    uint64_t cursor = 0;      // next pid not yet emitted
+    uint64_t suspended = 0;   // particles suspended at the end of the last epoch
     double flights_per_particle = 1.0;
-    unsigned long long stats[kStats] = {0, 0, 0, 0, 0};
+    unsigned long long stats[kStats] = {0, 0, 0, 0, 0, 0};
     double kernel_ms = 0.0;
     std::vector<double> host_tally;  // filled when complete
 };
@@ -100,12 +101,23 @@ struct dmc_server {
     uint64_t next_ticket = 1;
     std::vector<JobDev> epoch_table;  // upload sources of the running epoch
     std::vector<double> epoch_times;
+    // particles suspended at the end of the previous epoch (double-buffered)
+    Suspended *susp[2] = {nullptr, nullptr};
+    uint32_t susp_cap = 0;
+    int cur = 0;                     // buffer holding the previous epoch's suspended particles
+    uint32_t n_susp = 0;
+    std::vector<Request *> prev_members;
+    int32_t *d_resume_job = nullptr;
+    std::vector<int32_t> h_resume_job;
     ~dmc_server()
     {
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         if (arena_mem) (void)hipFree(arena_mem);
         if (scratch) (void)hipFree(scratch);
+        for (Suspended *p : susp)
+            if (p) (void)hipFree(p);
+        if (d_resume_job) (void)hipFree(d_resume_job);
     }
 };
 
@@ -158,6 +170,21 @@ extern "C" dmc_status dmc_server_create(const dmc_material *material, const dmc_
     S->sb.stats = (unsigned long long *)(p + jb + tb);
     S->sb.queue = (unsigned long long *)(p + jb + tb + stb);
     S->sb.tally = (double *)S->arena_mem;
+    // every lane of an epoch launch may suspend one particle
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    // each lane of an epoch may suspend its particle and each wave up to one
+    // chunk (<= 64) of unstarted indices: twice the resident lanes
+    S->susp_cap = (uint32_t)cus * 4096u;
+    for (int i = 0; i < 2; ++i)
+        if (hipMalloc(&S->susp[i], (size_t)S->susp_cap * sizeof(Suspended)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(DMC_E_NOMEM, "cannot allocate the suspended-particle buffers");
+        }
+    if (hipMalloc(&S->d_resume_job, (size_t)nj * sizeof(int32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DMC_E_NOMEM, "cannot allocate server scratch");
+    }
     DMC_HIP_OR_FAIL(hipEventCreate(&S->ev0));
     DMC_HIP_OR_FAIL(hipEventCreate(&S->ev1));
     *out = S.release();
@@ -193,6 +220,7 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
     std::vector<double> &times = S->epoch_times;
     times.clear();
     std::vector<Request *> members;
+    LaunchBuffers lb = S->sb;
     {
         std::lock_guard<std::mutex> g(S->mu);
         // admit in arrival order while a slot and memory are free
@@ -231,8 +259,32 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
             devs.push_back(d);
             members.push_back(r);
         }
+        // particles suspended last epoch resume first; their slots map to this
+        // epoch's job table (jobs are queued in member order, so index = member)
+        S->h_resume_job.assign((size_t)S->opts.max_active, 0);
+        for (size_t i = 0; i < S->prev_members.size(); ++i) {
+            int32_t idx = -1;
+            for (size_t j = 0; j < members.size(); ++j)
+                if (members[j] == S->prev_members[i]) idx = (int32_t)j;
+            if (idx < 0 && S->prev_members[i]->suspended)
+                return fail(DMC_E_DEVICE, "internal: a request with suspended particles left the epoch");
+            S->h_resume_job[i] = idx < 0 ? 0 : idx;
+        }
     }
-    dmc_status st = enqueue_launch(S->M, devs, times, S->epoch_table, S->sb, 0, false, S->opts.run, s, S->ev0, S->ev1);
+    DMC_HIP_OR_FAIL(hipMemcpyAsync(S->d_resume_job, S->h_resume_job.data(), S->h_resume_job.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, s));
+    // while requests still have unstarted particles, epochs stay short so new
+    // arrivals join quickly; once only continuations remain, they run longer
+    bool fresh = false;
+    for (size_t i = 0; i < members.size(); ++i) fresh = fresh || devs[i].n > 0;
+    const uint32_t drain = S->opts.drain_flights ? S->opts.drain_flights : 2048u;
+    lb.drain_iters = fresh ? drain : 16u * drain;
+    lb.n_resume = S->n_susp;
+    lb.resume_in = S->susp[S->cur];
+    lb.resume_job = S->d_resume_job;
+    lb.suspend_out = S->susp[1 - S->cur];
+    lb.suspend_cap = S->susp_cap;
+    dmc_status st = enqueue_launch(S->M, devs, times, S->epoch_table, lb, 0, false, S->opts.run, s, S->ev0, S->ev1);
     if (st != DMC_OK) return st;
     DMC_HIP_OR_FAIL(hipEventSynchronize(S->ev1));
     float ms = 0.0f;
@@ -241,15 +293,21 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
     DMC_HIP_OR_FAIL(hipMemcpy(stats.data(), S->sb.stats, stats.size() * 8, hipMemcpyDeviceToHost));
     int32_t finished = 0;
     std::lock_guard<std::mutex> g(S->mu);
+    uint64_t n_susp = 0;
     for (size_t i = 0; i < members.size(); ++i) {
         Request *r = members[i];
-        for (int k = 0; k < kStats; ++k) r->stats[k] += stats[i * kStats + k];
+        for (int k = 0; k < 5; ++k) r->stats[k] += stats[i * kStats + k];
+        r->suspended = stats[i * kStats + 5];
+        n_susp += r->suspended;
         r->kernel_ms += ms;
         r->cursor += devs[i].n;
     }
+    S->n_susp = (uint32_t)n_susp;
+    S->cur = 1 - S->cur;
+    S->prev_members = members;
     for (size_t i = 0; i < S->active.size();) {
         Request *r = S->active[i].get();
-        if (r->cursor >= r->jh.dev.n) {
+        if (r->cursor >= r->jh.dev.n && r->suspended == 0) {
             r->host_tally.assign((size_t)std::max<int64_t>(r->jh.size, 1), 0.0);
             DMC_HIP_OR_FAIL(hipMemcpy(r->host_tally.data(), (char *)S->arena_mem + r->arena_off,
                                       (size_t)r->jh.size * sizeof(double), hipMemcpyDeviceToHost));

@@ -50,7 +50,7 @@ def layout_probe(tmp_path_factory):
                          "workspace", "workspace_bytes", "nscat_out"],
         "dmc_job": ["material", "geometry", "source", "tally", "n_particles", "seed", "times", "n_times"],
         "dmc_stats": ["particles", "scatters", "boundary", "iterations", "capped", "kernel_ms"],
-        "dmc_server_opts": ["memory_budget", "max_active", "epoch_flights", "run"],
+        "dmc_server_opts": ["memory_budget", "max_active", "epoch_flights", "drain_flights", "run"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for s, fields in structs.items():
