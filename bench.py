@@ -86,6 +86,21 @@ def cpu_baseline(jobs, target_s=15.0):
             "sample": f"first {n} particles of each of the 12 films ({ev} scattering events, {dt:.1f} s)"}
 
 
+def launch_params(jobs, mat, precision="fp32", stream=None, overrides=None):
+    """Launch parameters of the timed configuration: the library's autotuner on
+    this batch (cached per process and batch signature), then any explicit
+    non-zero overrides."""
+    from paper_1206_3316_amd import binding as b
+
+    params, trials = b.autotune(jobs, material=mat, precision=precision, stream=stream)
+    if trials:
+        launch_params.trials = trials
+    for k, v in (overrides or {}).items():
+        if v:
+            params[k] = v
+    return params
+
+
 def flights_per_particle(job, sums):
     C_tot, G_tau, G_v = sums
     if job.source.kind == "walls":
@@ -105,8 +120,7 @@ def serve(b, di, torch, mat, mat_in, stream, capacity, n_requests, args):
     arrivals = di.poisson_arrivals(n_requests, rate)
     free, _ = torch.cuda.mem_get_info()
     budget = int(min(0.8 * free, 64 << 30))
-    srv = b.Server(mat, budget, max_active=32, epoch_flights=args.epoch_flights, stream=stream,
-                   chunk=args.chunk, refill_min=args.refill_min)
+    srv = b.Server(mat, budget, max_active=32, epoch_flights=args.epoch_flights, stream=stream, refill_min=4)
     lat, kinds, scat = [], [], 0
     pending = {}
     i = 0
@@ -137,7 +151,7 @@ def serve(b, di, torch, mat, mat_in, stream, capacity, n_requests, args):
                 lat.append(t_done - ta)
                 kinds.append(reqs[k][0])
                 if k < 2:  # the same request alone must give the same result
-                    solo = b.simulate([reqs[k][1]], material=mat, stream=stream, chunk=args.chunk)
+                    solo = b.simulate([reqs[k][1]], material=mat, stream=stream)
                     a, c = res.raw(0), solo.raw(0)
                     d = float(abs(a - c).max() / max(abs(c).max(), 1e-300))
                     serve.mix_vs_alone = max(getattr(serve, "mix_vs_alone", 0.0), d)
@@ -183,8 +197,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=float, default=1e8, help="particles per film")
     ap.add_argument("--plain-n", type=float, default=1e6, help="particles per film for the plain-form sample")
-    ap.add_argument("--chunk", type=int, default=4096)
-    ap.add_argument("--refill-min", type=int, default=4)
+    ap.add_argument("--chunk", type=int, default=0, help="queue chunk (0: autotuned)")
+    ap.add_argument("--refill-min", type=int, default=0, help="refill threshold (0: autotuned)")
+    ap.add_argument("--block", type=int, default=0, help="workgroup size (0: autotuned)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -211,10 +226,15 @@ def main():
     stream = torch.cuda.current_stream()
     nbytes = b.workspace_bytes(jobs, mat)
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    t_tune = time.perf_counter()
+    params = launch_params(jobs, mat, stream=stream,
+                           overrides={"chunk": args.chunk, "refill_min": args.refill_min, "block": args.block})
+    log(f"launch parameters {params} (autotuner {time.perf_counter() - t_tune:.1f} s, "
+        f"{len(getattr(launch_params, 'trials', []))} trials)")
 
     def step():
         r = b.simulate(jobs, material=mat, precision="fp32", form="persistent", stream=stream, workspace=ws,
-                       chunk=args.chunk, refill_min=args.refill_min)
+                       **params)
         return r, r.stats(-1)
 
     for i in range(args.warmup):
@@ -243,7 +263,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32 flight / f64 tally", "data": "synthetic",
         "config": {"workload": "12 silicon-like cross-plane films 10 nm - 10 um, 1e8 particles each "
                                "(1000 omega bins x LA+2TA, walls T_eq +- 0.5 K, 20 bins), one persistent launch",
-                   "particles_per_step": parts // args.steps},
+                   "particles_per_step": parts // args.steps, "launch": params},
         "particles_per_s": parts / wall,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,

@@ -180,6 +180,7 @@ class Job:
     n_particles: int
     seed: int
     name: str = ""
+    first_particle: int = 0   # simulate pids first_particle .. first_particle + n_particles - 1
 
 
 # --------------------------------------------------------------------------

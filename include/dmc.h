@@ -166,8 +166,9 @@ typedef struct {
     int32_t grid_blocks;   /* persistent: workgroups to launch; 0 = fill the device */
     void *workspace;       /* optional caller-owned device memory for tallies and queues */
     size_t workspace_bytes;
-    uint32_t *nscat_out;   /* optional device array: scattering events of every particle,
-                              indexed by the job's pid offset in the launch plus pid */
+    uint32_t *nscat_out;   /* optional device array (sum of the jobs' n_particles entries): the
+                              scattering events of particle pid of job j are written at
+                              (n_particles of jobs 0..j-1) + pid; not used by the server */
 } dmc_run_opts;
 
 /* Fills opts with the defaults (FP32 + FP64 tallies, persistent, auto parameters). */
@@ -183,6 +184,11 @@ typedef struct {
     uint64_t seed;        /* Philox key */
     const double *times;  /* transient snapshot times [s], ascending, > 0; NULL for steady */
     int32_t n_times;      /* <= 1024; the last time is t_final */
+    int32_t pad0;
+    uint64_t first_particle; /* particles first_particle .. first_particle + n_particles - 1 of the
+                                seed's realisation are simulated (0 for a whole run). A slice is an
+                                estimate on its own (normalised by its n_particles); the raw sums
+                                (DMC_Q_RAW) of disjoint slices add up to those of the union. */
 } dmc_job;
 
 typedef struct dmc_result dmc_result;
@@ -199,6 +205,47 @@ dmc_status dmc_simulate(const dmc_material *material, const dmc_geometry *geomet
  * over all jobs; plain form: one launch per job on the same stream).
  * Asynchronous on opts->stream. */
 dmc_status dmc_simulate_batch(const dmc_job *jobs, int32_t n_jobs, const dmc_run_opts *opts, dmc_result **out);
+
+/* ---- Autotuner (persistent form) ----
+ * Picks block size, queue chunk, refill threshold and tally privatisation for a
+ * batch by timing trial launches of a sample of it.  The sample cuts every job
+ * to the first part of its particle range, sized so that a trial runs about
+ * sample_flights flights in total, and stops each trajectory after trial_cap
+ * flights, so that a trial measures the bulk rate rather than the single
+ * longest trajectory of a heavy-tailed job.  The parameters are searched one
+ * at a time from the defaults (tally privatisation, block, chunk, refill
+ * threshold); a candidate replaces the current choice only when it is at least
+ * 2 % faster.  Unprivatised tallies (global FP64 atomics, which can serialise
+ * on a few contended sums) are first screened on 1/16 of the sample and
+ * dropped when that alone takes longer than the current choice.  None of these parameters changes an estimate: they move FP64
+ * additions between registers, LDS and HBM, nothing else.
+ * The choice is cached for the life of the process per material, precision and
+ * batch signature (every job's geometry, source kind, tally shape and the
+ * order of magnitude of its particle count).
+ * Synchronous; runs on base->stream; allocates and frees its own sample
+ * workspace.  For the plain form it returns *base unchanged with no trials. */
+typedef struct {
+    int32_t block, chunk, refill_min, lds_tally;
+    int32_t pilot;         /* 1: a screening run on 1/16 of the sample (unprivatised tallies only) */
+    int32_t pad0;
+    double ms;             /* trial kernel time */
+    double flights_per_s;  /* trial flights / trial kernel time */
+} dmc_tune_trial;
+
+typedef struct {
+    uint64_t sample_flights; /* 0: 5e10 */
+    uint32_t trial_cap;      /* 0: 4096 flights */
+    int32_t use_cache;       /* 1: reuse the cached choice for the same signature */
+    dmc_tune_trial *trials;  /* optional host array receiving the trials in order */
+    int32_t max_trials;
+    int32_t n_trials;        /* out: trials run (0 when the cache answered) */
+    int32_t from_cache;      /* out */
+} dmc_tune_opts;
+
+/* best receives *base with block, chunk, refill_min and lds_tally set and
+ * grid_blocks 0.  tune may be NULL (defaults, cache on). */
+dmc_status dmc_autotune(const dmc_job *jobs, int32_t n_jobs, const dmc_run_opts *base, dmc_tune_opts *tune,
+                        dmc_run_opts *best);
 
 #define DMC_Q_T 0          /* energy temperature T - T_eq per bin [K] (n = n_bins) */
 #define DMC_Q_TLOC 1       /* pseudo-temperature T_loc - T_eq per bin [K] */

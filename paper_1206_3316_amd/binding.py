@@ -62,12 +62,23 @@ class dmc_run_opts(C.Structure):
 class dmc_job(C.Structure):
     _fields_ = [("material", C.c_void_p), ("geometry", C.c_void_p), ("source", dmc_source),
                 ("tally", dmc_tally_desc), ("n_particles", C.c_uint64), ("seed", C.c_uint64),
-                ("times", f64p), ("n_times", C.c_int32)]
+                ("times", f64p), ("n_times", C.c_int32), ("pad0", C.c_int32), ("first_particle", C.c_uint64)]
 
 
 class dmc_stats(C.Structure):
     _fields_ = [("particles", C.c_uint64), ("scatters", C.c_uint64), ("boundary", C.c_uint64),
                 ("iterations", C.c_uint64), ("capped", C.c_uint64), ("kernel_ms", C.c_double)]
+
+
+class dmc_tune_trial(C.Structure):
+    _fields_ = [("block", C.c_int32), ("chunk", C.c_int32), ("refill_min", C.c_int32), ("lds_tally", C.c_int32),
+                ("pilot", C.c_int32), ("pad0", C.c_int32), ("ms", C.c_double), ("flights_per_s", C.c_double)]
+
+
+class dmc_tune_opts(C.Structure):
+    _fields_ = [("sample_flights", C.c_uint64), ("trial_cap", C.c_uint32), ("use_cache", C.c_int32),
+                ("trials", C.POINTER(dmc_tune_trial)), ("max_trials", C.c_int32), ("n_trials", C.c_int32),
+                ("from_cache", C.c_int32)]
 
 
 class dmc_server_opts(C.Structure):
@@ -91,6 +102,8 @@ _SIGS = {
                      C.c_int32),
     "dmc_simulate_batch": ([C.POINTER(dmc_job), C.c_int32, C.POINTER(dmc_run_opts), C.POINTER(C.c_void_p)],
                            C.c_int32),
+    "dmc_autotune": ([C.POINTER(dmc_job), C.c_int32, C.POINTER(dmc_run_opts), C.POINTER(dmc_tune_opts),
+                      C.POINTER(dmc_run_opts)], C.c_int32),
     "dmc_tally_read": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, f64p, f64p, C.c_size_t], C.c_int32),
     "dmc_tally_raw_size": ([C.c_void_p, C.c_int32, C.POINTER(C.c_size_t)], C.c_int32),
     "dmc_result_stats": ([C.c_void_p, C.c_int32, C.POINTER(dmc_stats)], C.c_int32),
@@ -181,6 +194,10 @@ def dmc_simulate(material, geometry, source, n_particles, seed, tally, times, n_
 
 def dmc_simulate_batch(jobs, n_jobs, opts, out):
     return _call("dmc_simulate_batch", jobs, n_jobs, opts, out)
+
+
+def dmc_autotune(jobs, n_jobs, base, tune, best):
+    return _call("dmc_autotune", jobs, n_jobs, base, tune, best)
 
 
 def dmc_tally_read(res, job, quantity, time_index, mean, se, n):
@@ -338,6 +355,7 @@ def job_struct(job, material: Material, keep: list) -> dmc_job:
     j.seed = int(job.seed)
     j.times = _ptr(times, C.c_double) if times.shape[0] else f64p()
     j.n_times = int(times.shape[0])
+    j.first_particle = int(getattr(job, "first_particle", 0))
     return j
 
 
@@ -437,6 +455,37 @@ def simulate(jobs, material: Optional[Material] = None, precision="fp32", form="
     h = C.c_void_p()
     dmc_simulate_batch(arr, len(jobs), C.byref(o), C.byref(h))
     return Result(h, jobs, keep)
+
+
+TUNED_PARAMS = ("block", "chunk", "refill_min", "lds_tally")
+
+
+def autotune(jobs, material: Optional[Material] = None, precision="fp32", stream=None, sample_flights=0,
+             trial_cap=0, use_cache=True):
+    """Launch parameters for ``simulate`` chosen by the library's autotuner.
+
+    Returns (params, trials): params is a dict of block / chunk / refill_min /
+    lds_tally to pass to ``simulate``; trials lists the timed trials (empty when
+    the process-wide cache answered).
+    """
+    if not isinstance(jobs, (list, tuple)):
+        jobs = [jobs]
+    material = material or Material(jobs[0].material)
+    keep: list = [material]
+    arr = (dmc_job * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = job_struct(j, material, keep)
+    base = run_opts(precision, "persistent", getattr(stream, "cuda_stream", stream))
+    t = dmc_tune_opts()
+    t.sample_flights, t.trial_cap, t.use_cache = int(sample_flights), int(trial_cap), int(bool(use_cache))
+    buf = (dmc_tune_trial * 64)()
+    t.trials = buf
+    t.max_trials = 64
+    best = dmc_run_opts()
+    dmc_autotune(arr, len(jobs), C.byref(base), C.byref(t), C.byref(best))
+    trials = [{"block": r.block, "chunk": r.chunk, "refill_min": r.refill_min, "lds_tally": r.lds_tally,
+               "pilot": r.pilot, "ms": r.ms, "flights_per_s": r.flights_per_s} for r in buf[:min(t.n_trials, 64)]]
+    return {k: int(getattr(best, k)) for k in TUNED_PARAMS}, trials
 
 
 def workspace_bytes(jobs, material: Material, precision="fp32", form="persistent") -> int:

@@ -160,6 +160,8 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
     const dmc_source &s = jb.source;
     const dmc_tally_desc &t = jb.tally;
     if (jb.n_particles < 1) return fail(DMC_E_INVALID, "n_particles must be >= 1");
+    if (jb.first_particle + jb.n_particles < jb.first_particle)
+        return fail(DMC_E_INVALID, "first_particle + n_particles overflows");
     if (t.n_bins < 0 || t.n_bins > kMaxBins) return fail(DMC_E_INVALID, "n_bins out of range");
     if (t.n_batches < 2 || t.n_batches > 256) return fail(DMC_E_INVALID, "n_batches must be 2..256");
     if (t.kmax < -1) return fail(DMC_E_INVALID, "kmax must be >= -1");
@@ -177,6 +179,7 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
     JobDev &d = h.dev;
     std::memset(&d, 0, sizeof(d));
     d.n = jb.n_particles;
+    d.pid0 = jb.first_particle;
     d.key0 = (uint32_t)jb.seed;
     d.key1 = (uint32_t)(jb.seed >> 32);
     d.geom = g.kind;
@@ -285,9 +288,19 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
         o += (int64_t)jb.n_times * (d.ncell + 1);
         d.off_snap_abs = o;
         o += (int64_t)jb.n_times * (d.ncell + 1);
+        // a Gaussian initial condition gives every particle the sign of dT, so
+        // sum |s| = |sum s| per cell: the device skips that second atomic
+        d.snap_abs_on = (s.kind == DMC_SRC_GAUSSIAN) ? 0 : 1;
     }
     h.size = o;
     return DMC_OK;
+}
+
+void complete_tally(const JobDev &d, double *block)
+{
+    if (d.off_snap_abs < 0 || d.snap_abs_on) return;
+    const int64_t n = (int64_t)d.n_times * (d.ncell + 1);
+    for (int64_t i = 0; i < n; ++i) block[d.off_snap_abs + i] = std::fabs(block[d.off_snap + i]);
 }
 
 dmc_status run_opts_check(const dmc_run_opts &o)
@@ -316,14 +329,25 @@ int device_cus()
 
 // ----------------------------------------------------------- launch plan ----
 
+int kernel_spec(const JobDev *jobs, int n_jobs)
+{
+    bool slab = true, half = true;
+    for (int i = 0; i < n_jobs; ++i) {
+        const JobDev &d = jobs[i];
+        if (d.geom != GEOM_SLAB || d.src != SRC_WALLS || d.n_times > 0) slab = false;
+        if (d.geom != GEOM_HALF || d.src != SRC_GAUSSIAN || d.n_times == 0 || d.n_bins > 0 || d.off_kappa >= 0 ||
+            d.n_hj > 0)
+            half = false;
+    }
+    return slab ? (int)GEOM_SLAB : half ? (int)GEOM_HALF : (int)GEOM_ANY;
+}
+
 dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, const std::vector<double> &times,
                           std::vector<JobDev> &table, const LaunchBuffers &b, size_t tally_doubles, bool zero_tally,
                           const dmc_run_opts &o, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     const int n_jobs = (int)devs.size();
-    bool slab_only = true;
-    for (auto &d : devs)
-        if (d.geom != GEOM_SLAB || d.src != SRC_WALLS || d.n_times > 0) slab_only = false;
+    const int spec = kernel_spec(devs.data(), n_jobs);
     KArgs a{};
     a.jobs = b.jobs;
     a.n_jobs = n_jobs;
@@ -352,6 +376,7 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
     a.resume_job = b.resume_job;
     a.suspend_out = b.suspend_out;
     a.suspend_cap = b.suspend_cap;
+    a.iter_cap = b.iter_cap ? std::min(b.iter_cap, kIterCap) : kIterCap;
     a.total += b.n_resume;
     if ((b.drain_iters || b.n_resume) && o.form != DMC_FORM_PERSISTENT)
         return fail(DMC_E_INVALID, "time-bounded launches need the persistent form");
@@ -393,7 +418,7 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
         a.refill_min = o.refill_min > 0 ? o.refill_min : 16;
         block = o.block > 0 ? o.block : (lds_bytes > 64 * 1024 ? 1024 : 512);
         const bool bounded = b.drain_iters > 0 || b.n_resume > 0;
-        const int per_cu = occupancy_blocks(o.precision, o.form, slab_only && !bounded, bounded, block, lds_bytes);
+        const int per_cu = occupancy_blocks(o.precision, o.form, bounded ? (int)GEOM_ANY : spec, bounded, block, lds_bytes);
         grid = o.grid_blocks > 0 ? o.grid_blocks : device_cus() * per_cu;
         if (b.drain_iters) {
             // every lane may suspend one particle and every wave the unstarted rest of
@@ -421,7 +446,7 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
     DMC_HIP_OR_FAIL(launch_fill(nullptr, 0, b.queue, 2, s));
     DMC_HIP_OR_FAIL(hipEventRecord(ev0, s));
     if (o.form == DMC_FORM_PERSISTENT) {
-        DMC_HIP_OR_FAIL(launch_trajectories(a, o.precision, o.form, slab_only, block, grid, lds_bytes, s));
+        DMC_HIP_OR_FAIL(launch_trajectories(a, o.precision, o.form, spec, block, grid, lds_bytes, s));
     } else {
         // one launch per simulation, in order, on the same stream
         for (int i = 0; i < n_jobs; ++i) {
@@ -430,8 +455,8 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
             aj.total = devs[i].base + devs[i].n;
             const uint64_t blocks = (devs[i].n + 255) / 256;
             if (blocks > 0x7fffffffull) return fail(DMC_E_INVALID, "too many particles for one plain launch");
-            const bool slab = (devs[i].geom == GEOM_SLAB && devs[i].src == SRC_WALLS && devs[i].n_times == 0);
-            DMC_HIP_OR_FAIL(launch_trajectories(aj, o.precision, o.form, slab, 256, (int)blocks, lds_bytes, s));
+            DMC_HIP_OR_FAIL(launch_trajectories(aj, o.precision, o.form, kernel_spec(&devs[i], 1), 256, (int)blocks,
+                                                lds_bytes, s));
         }
     }
     DMC_HIP_OR_FAIL(hipEventRecord(ev1, s));
@@ -449,7 +474,7 @@ extern "C" void dmc_run_opts_default(dmc_run_opts *o)
     o->lds_tally = 1;
 }
 
-namespace {
+namespace dmc {
 
 struct Layout {
     size_t jobs_off, times_off, tally_off, stats_off, queue_off, total;
@@ -513,10 +538,12 @@ dmc_status gather_jobs(const dmc_job *jobs, int32_t n_jobs, std::vector<JobHost>
         base += d.n;
     }
     int64_t toff = 0, tim = 0;
+    uint64_t out = 0;
     for (int i = 0; i < n_jobs; ++i) {
         JobDev &d = jh[i].dev;
-        d.pid0 = 0;
         d.stat_slot = i;
+        d.out_off = out;
+        out += d.n;
         if (d.off_bins >= 0) d.off_bins += toff;
         if (d.off_kappa >= 0) d.off_kappa += toff;
         if (d.off_hj >= 0) d.off_hj += toff;
@@ -529,7 +556,7 @@ dmc_status gather_jobs(const dmc_job *jobs, int32_t n_jobs, std::vector<JobHost>
     return DMC_OK;
 }
 
-dmc_status launch(std::vector<JobHost> &jh, const dmc_run_opts &o, dmc_result **out)
+dmc_status launch(std::vector<JobHost> &jh, const dmc_run_opts &o, dmc_result **out, uint32_t iter_cap)
 {
     *out = nullptr;
     const dmc_material *M = jh[0].job.material;
@@ -561,6 +588,7 @@ dmc_status launch(std::vector<JobHost> &jh, const dmc_run_opts &o, dmc_result **
     b.tally = (double *)(base + L.tally_off);
     b.stats = (unsigned long long *)(base + L.stats_off);
     b.queue = (unsigned long long *)(base + L.queue_off);
+    b.iter_cap = iter_cap;
     R->d_tally = b.tally;
     R->d_stats = b.stats;
     R->tally_doubles = L.tally_doubles;
@@ -584,6 +612,8 @@ dmc_status launch(std::vector<JobHost> &jh, const dmc_run_opts &o, dmc_result **
     return DMC_OK;
 }
 
+size_t workspace_bytes(const std::vector<JobHost> &jh) { return layout_of(jh).total; }
+
 dmc_status sync_result(dmc_result *R)
 {
     if (R->synced) return DMC_OK;
@@ -593,6 +623,7 @@ dmc_status sync_result(dmc_result *R)
     R->kernel_ms = ms;
     R->h_tally.assign(std::max<size_t>(R->tally_doubles, 1), 0.0);
     HIP_OR_FAIL(hipMemcpy(R->h_tally.data(), R->d_tally, R->tally_doubles * sizeof(double), hipMemcpyDeviceToHost));
+    for (const auto &h : R->jobs) complete_tally(h.dev, R->h_tally.data());
     R->h_stats.assign(R->jobs.size() * kStats, 0ull);
     HIP_OR_FAIL(hipMemcpy(R->h_stats.data(), R->d_stats, R->h_stats.size() * sizeof(unsigned long long),
                           hipMemcpyDeviceToHost));
@@ -600,7 +631,7 @@ dmc_status sync_result(dmc_result *R)
     return DMC_OK;
 }
 
-}  // namespace
+}  // namespace dmc
 
 extern "C" dmc_status dmc_workspace_size(const dmc_job *jobs, int32_t n_jobs, const dmc_run_opts *opts, size_t *bytes)
 {
@@ -609,7 +640,7 @@ extern "C" dmc_status dmc_workspace_size(const dmc_job *jobs, int32_t n_jobs, co
     std::vector<JobHost> jh;
     dmc_status st = gather_jobs(jobs, n_jobs, jh);
     if (st != DMC_OK) return st;
-    *bytes = layout_of(jh).total;
+    *bytes = workspace_bytes(jh);
     (void)opts;
     return DMC_OK;
 }
@@ -766,7 +797,7 @@ extern "C" dmc_status dmc_simulate(const dmc_material *material, const dmc_geome
         if (out) *out = nullptr;
         return fail(DMC_E_INVALID, "source / tally is NULL");
     }
-    dmc_job j;
+    dmc_job j{};
     j.material = material;
     j.geometry = geometry;
     j.source = *source;

@@ -43,6 +43,9 @@ struct JobHost {
 };
 
 dmc_status prepare_job(const dmc_job &jb, JobHost &h);
+// Host-side completion of a job's tally block after the copy from the device
+// (offsets of d relative to block): fills the sections the device skips.
+void complete_tally(const JobDev &d, double *block);
 dmc_status run_opts_check(const dmc_run_opts &o);
 
 // Device regions a launch uses besides the material tables.
@@ -59,6 +62,9 @@ struct LaunchBuffers {
     const int32_t *resume_job = nullptr;
     Suspended *suspend_out = nullptr;
     uint32_t suspend_cap = 0;
+    // autotuner trials stop trajectories early so that a sample measures the
+    // bulk rate rather than its longest particle; 0 = the safety cap
+    uint32_t iter_cap = 0;
 };
 
 // Plans LDS privatisation and occupancy, uploads the descriptors, clears the
@@ -70,6 +76,17 @@ struct LaunchBuffers {
 dmc_status enqueue_launch(const struct ::dmc_material *M, std::vector<JobDev> &devs, const std::vector<double> &times,
                           std::vector<JobDev> &table, const LaunchBuffers &b, size_t tally_doubles, bool zero_tally,
                           const dmc_run_opts &o, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1);
+
+// Validates a batch and prepares its jobs (queue order, tally offsets).
+dmc_status gather_jobs(const dmc_job *jobs, int32_t n_jobs, std::vector<JobHost> &jh);
+// Expected flights per particle of a prepared job (queue order, tuner sample sizes).
+double flights_per_particle(const struct ::dmc_material &M, const JobHost &h);
+// Device bytes a batch needs (descriptors, times, tallies, counters, queue).
+size_t workspace_bytes(const std::vector<JobHost> &jh);
+// Enqueues a batch (consumes jh) and returns its result handle.
+dmc_status launch(std::vector<JobHost> &jh, const dmc_run_opts &o, ::dmc_result **out, uint32_t iter_cap = 0);
+// Waits for a result and copies its tallies and counters to the host.
+dmc_status sync_result(::dmc_result *R);
 
 }  // namespace dmc
 

@@ -49,7 +49,8 @@ struct alignas(16) JobDev {
     double grid_lo[3], grid_ext[3];  // lower bound and extent hi - lo
     int64_t ncell;
     int32_t stat_slot;      // index of this job's counters (the caller's job index)
-    int32_t pad1;
+    int32_t snap_abs_on;    // 0: every particle has the same sign, the host derives sum|s| = |sum s|
+    uint64_t out_off;       // per-particle outputs of pid are at out_off + pid - pid0 (caller's job order)
 };
 
 // A particle suspended at the end of a time-bounded launch (serving epochs):
@@ -75,7 +76,7 @@ struct KArgs {
     const double2 *st64;            // per state: v, tau
     double *tally;
     const double *times;
-    uint32_t *nscat_out;            // optional, indexed by queue index
+    uint32_t *nscat_out;            // optional, indexed by JobDev::out_off + pid
     unsigned long long *stats;      // [n_jobs][kStats]
     int32_t chunk, refill_min;
     int32_t lds_tally_doubles;      // LDS tally size; 0 = none
@@ -90,6 +91,7 @@ struct KArgs {
     const int32_t *resume_job;      // device-table job of each resumed particle's slot
     Suspended *suspend_out;
     uint32_t suspend_cap;
+    uint32_t iter_cap;              // flights after which a particle is stopped and counted as capped
 };
 
 // Packed alias entry: column idx of a table with b index bits keeps idx iff
@@ -105,7 +107,9 @@ inline uint32_t pack_alias(uint32_t thresh, uint32_t alias, uint32_t idx, int bi
 }
 
 // Launch entry points (dmc_kernels.hip).
-hipError_t launch_trajectories(const KArgs &a, int precision, int form, bool slab_only, int block, int grid,
+// spec: GEOM_SLAB (every job a steady wall-driven slab), GEOM_HALF (every job a
+// transient half-space Gaussian with snapshots only) or GEOM_ANY.
+hipError_t launch_trajectories(const KArgs &a, int precision, int form, int spec, int block, int grid,
                                size_t lds_bytes, hipStream_t stream);
 hipError_t launch_fill(double *p, size_t n_doubles, unsigned long long *q, size_t n_u64, hipStream_t stream);
 hipError_t launch_debug_philox(uint64_t seed, const uint64_t *pid, const uint32_t *k, const uint32_t *tag,
@@ -114,6 +118,8 @@ hipError_t launch_debug_alias(const uint32_t *packed, int bits, const uint32_t *
                               hipStream_t stream);
 hipError_t launch_debug_math(const double *x, double *lg, double *sn, double *cs, size_t n, hipStream_t stream);
 int max_lds_bytes();
-int occupancy_blocks(int precision, int form, bool slab_only, bool bounded, int block, size_t lds_bytes);
+int occupancy_blocks(int precision, int form, int spec, bool bounded, int block, size_t lds_bytes);
+// The specialised kernel a set of jobs can use.
+int kernel_spec(const JobDev *jobs, int n_jobs);
 
 }  // namespace dmc

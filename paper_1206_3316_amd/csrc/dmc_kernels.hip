@@ -19,7 +19,9 @@
 //                     refill free lanes; gain table and state data staged in
 //                     LDS; per-lane bin caches flushed to LDS-privatised
 //                     tallies that are added to HBM once per workgroup
-//   G      GEOM_SLAB  cross-plane slab only (dead components eliminated)
+//   G      GEOM_SLAB  cross-plane slab, wall sources, steady (dead components
+//                     eliminated)
+//          GEOM_HALF  half space, Gaussian initial condition, snapshots only
 //          GEOM_ANY   every geometry and source, chosen per lane
 //
 // Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = seed and
@@ -181,7 +183,7 @@ struct Lane {
     R s;                    // sign
     int32_t last;           // surface the particle rests on (excluded from the next search)
     uint32_t k, nscat, nbound;
-    uint64_t pid, qidx;
+    uint64_t pid;
     int32_t job, batch, slot;
     // cached job parameters
     int32_t geom, src, n_bins, n_hj, kmax, n_times;
@@ -196,6 +198,7 @@ struct Lane {
     int32_t cbin;
     double c0, c1, c2;
     int32_t tcur;
+    double tnext, tend;  // next snapshot time and final time (+inf when steady)
 };
 
 struct Shared {
@@ -307,12 +310,20 @@ __device__ __forceinline__ void bind_job(Lane<R> &p, const JobDev &J, uint64_t p
     p.c0 = p.c1 = p.c2 = 0.0;
 }
 
+// Keeps the next snapshot time and the final time in registers.
+template <typename R>
+__device__ __forceinline__ void set_times(Lane<R> &p, const KArgs &a, const JobDev &J)
+{
+    const double *times = a.times + J.times_off;
+    p.tnext = (p.tcur < p.n_times) ? times[p.tcur] : __builtin_huge_val();
+    p.tend = (p.n_times > 0) ? times[p.n_times - 1] : __builtin_huge_val();
+}
+
 template <typename R, int G>
 __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, uint64_t qidx, int job)
 {
     const uint64_t pid = J.pid0 + (qidx - J.base - (uint64_t)a.n_resume);
     bind_job<R, G>(p, J, pid, job);
-    p.qidx = qidx;
     p.x = p.y = p.z = (R)0;
     p.last = kNoSurface;
     p.k = 0;
@@ -322,11 +333,12 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
     p.Lz = 0.0;
     p.h = 0.0;
     p.tcur = 0;
+    set_times(p, a, J);
 
     const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
     const uint4 A = philox(plo, phi, 0u, TAG_EMIT_A, p.key0, p.key1);
     uint32_t m;
-    const int src = (G == GEOM_SLAB) ? (int)SRC_WALLS : p.src;
+    const int src = (G == GEOM_SLAB) ? (int)SRC_WALLS : (G == GEOM_HALF) ? (int)SRC_GAUSSIAN : p.src;
     if (src == SRC_WALLS) {
         const uint32_t j = (J.n_src > 1) ? alias_draw(J.src_packed, 1, A.x) : 0u;
         const int wall = J.src_wall[j];
@@ -493,10 +505,11 @@ __device__ void score_snapshots(Lane<R> &p, const KArgs &a, const JobDev &J, dou
             const int64_t cell = inside ? (idx[2] * J.grid[1] + idx[1]) * J.grid[0] + idx[0] : J.ncell;
             const int64_t o = (int64_t)p.tcur * (J.ncell + 1) + cell;
             gadd(a.tally + J.off_snap + o, (double)p.s);
-            gadd(a.tally + J.off_snap_abs + o, 1.0);
+            if (J.snap_abs_on) gadd(a.tally + J.off_snap_abs + o, 1.0);
         }
         ++p.tcur;
     }
+    p.tnext = (p.tcur < p.n_times) ? times[p.tcur] : __builtin_huge_val();
 }
 
 // ------------------------------------------------------ boundary search ----
@@ -666,7 +679,6 @@ __device__ void resume(Lane<R> &p, const KArgs &a, const Shared &sh, uint32_t i)
     const int job = a.resume_job[S.slot];
     const JobDev &J = a.jobs[job];
     bind_job<R, G>(p, J, S.pid, job);
-    p.qidx = J.base + (uint64_t)a.n_resume + (S.pid - J.pid0);  // only used for nscat_out, which the server does not set
     p.x = (R)S.x;
     p.y = (R)S.y;
     p.z = (R)S.z;
@@ -681,6 +693,7 @@ __device__ void resume(Lane<R> &p, const KArgs &a, const Shared &sh, uint32_t i)
     p.nbound = S.nbound;
     p.last = S.last;
     p.tcur = S.tcur;
+    set_times(p, a, J);
     p.s = (R)S.sign;
     load_state(p, a, sh, S.m);
 }
@@ -699,7 +712,7 @@ __device__ void finish(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDe
         tadd(a, sh, p.hl, p.hg, (int32_t)p.nscat, p.h);
         tadd(a, sh, p.hl, p.hg, p.n_hj + (int32_t)p.nscat, p.h * p.h);
     }
-    if (a.nscat_out) a.nscat_out[p.qidx] = p.nscat;
+    if (a.nscat_out) a.nscat_out[J.out_off + (p.pid - J.pid0)] = p.nscat;
     const unsigned long long vals[kStats] = {1ull, p.nscat, p.nbound, p.k, capped ? 1ull : 0ull};
     if (a.lds_stats) {
 #pragma unroll
@@ -728,16 +741,17 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
     const bool boundary = (tb <= dt);
     const R seg = boundary ? tb : dt;
     // step V: sample the segment
-    if (p.n_bins > 0) score_bins<R, FORM>(p, a, sh, J, seg);
+    if (G != GEOM_HALF && p.n_bins > 0) score_bins<R, FORM>(p, a, sh, J, seg);
     const bool gradient = (G == GEOM_ANY) && (p.src == SRC_GRADIENT);
     if (gradient) {
         const double dz = (double)(p.s * p.v * p.oz * seg);
         p.Lz += dz;
         if (p.nscat < (uint32_t)p.n_hj) p.h += dz;
     }
-    if (G == GEOM_ANY && p.n_times > 0) {
-        score_snapshots(p, a, J, (double)seg);
-        if (p.t + (double)seg > a.times[J.times_off + p.n_times - 1]) return 1;  // step VI
+    if (G != GEOM_SLAB) {
+        const double tb_abs = p.t + (double)seg;
+        if (p.tnext < tb_abs) score_snapshots(p, a, J, (double)seg);
+        if (tb_abs > p.tend) return 1;  // step VI
     }
     // move
     p.x += p.v * p.ox * seg;
@@ -771,7 +785,7 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
         ++p.nscat;
         if (p.kmax >= 0 && p.nscat >= (uint32_t)p.kmax) return 1;
     }
-    if (p.k >= kIterCap) return 2;
+    if (p.k >= a.iter_cap) return 2;
     return 0;
 }
 
@@ -1045,19 +1059,25 @@ const void *kernel_ptr(int form, bool bounded)
     return bounded ? (const void *)persistent_kernel<R, GEOM_ANY, true> : (const void *)persistent_kernel<R, G, false>;
 }
 
-const void *pick_kernel(int precision, int form, bool slab_only, bool bounded)
+template <typename R>
+const void *pick_geom(int spec, int form, bool bounded)
 {
-    if (precision == 0)
-        return slab_only ? kernel_ptr<double, GEOM_SLAB>(form, bounded) : kernel_ptr<double, GEOM_ANY>(form, bounded);
-    return slab_only ? kernel_ptr<float, GEOM_SLAB>(form, bounded) : kernel_ptr<float, GEOM_ANY>(form, bounded);
+    if (spec == GEOM_SLAB) return kernel_ptr<R, GEOM_SLAB>(form, bounded);
+    if (spec == GEOM_HALF) return kernel_ptr<R, GEOM_HALF>(form, bounded);
+    return kernel_ptr<R, GEOM_ANY>(form, bounded);
+}
+
+const void *pick_kernel(int precision, int form, int spec, bool bounded)
+{
+    return precision == 0 ? pick_geom<double>(spec, form, bounded) : pick_geom<float>(spec, form, bounded);
 }
 
 }  // namespace
 
-hipError_t launch_trajectories(const KArgs &a, int precision, int form, bool slab_only, int block, int grid,
+hipError_t launch_trajectories(const KArgs &a, int precision, int form, int spec, int block, int grid,
                                size_t lds_bytes, hipStream_t stream)
 {
-    const void *f = pick_kernel(precision, form, slab_only, a.drain_iters > 0 || a.n_resume > 0);
+    const void *f = pick_kernel(precision, form, spec, a.drain_iters > 0 || a.n_resume > 0);
     if (lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
@@ -1097,9 +1117,9 @@ hipError_t launch_debug_alias(const uint32_t *packed, int bits, const uint32_t *
 
 int max_lds_bytes() { return 160 * 1024; }
 
-int occupancy_blocks(int precision, int form, bool slab_only, bool bounded, int block, size_t lds_bytes)
+int occupancy_blocks(int precision, int form, int spec, bool bounded, int block, size_t lds_bytes)
 {
-    const void *f = pick_kernel(precision, form, slab_only, bounded);
+    const void *f = pick_kernel(precision, form, spec, bounded);
     if (lds_bytes > 64 * 1024) {
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess) {
             (void)hipGetLastError();

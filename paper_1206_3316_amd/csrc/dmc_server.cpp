@@ -251,7 +251,7 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
             if (d.off_snap_abs >= 0) d.off_snap_abs += shift;
             d.base = base;
             d.n = n;
-            d.pid0 = r->cursor;
+            d.pid0 = r->jh.dev.pid0 + r->cursor;
             d.stat_slot = (int32_t)devs.size();
             d.times_off = (int32_t)times.size();
             times.insert(times.end(), r->jh.times.begin(), r->jh.times.end());
@@ -311,6 +311,7 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
             r->host_tally.assign((size_t)std::max<int64_t>(r->jh.size, 1), 0.0);
             DMC_HIP_OR_FAIL(hipMemcpy(r->host_tally.data(), (char *)S->arena_mem + r->arena_off,
                                       (size_t)r->jh.size * sizeof(double), hipMemcpyDeviceToHost));
+            complete_tally(r->jh.dev, r->host_tally.data());
             S->arena->release(r->arena_off);
             S->done[r->ticket] = std::move(S->active[i]);
             S->active.erase(S->active.begin() + (long)i);

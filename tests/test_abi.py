@@ -48,9 +48,13 @@ def layout_probe(tmp_path_factory):
         "dmc_tally_desc": ["n_bins", "n_batches", "kmax", "n_hj", "grid", "grid_lo", "grid_hi"],
         "dmc_run_opts": ["precision", "form", "stream", "block", "chunk", "refill_min", "lds_tally", "grid_blocks",
                          "workspace", "workspace_bytes", "nscat_out"],
-        "dmc_job": ["material", "geometry", "source", "tally", "n_particles", "seed", "times", "n_times"],
+        "dmc_job": ["material", "geometry", "source", "tally", "n_particles", "seed", "times", "n_times",
+                    "first_particle"],
         "dmc_stats": ["particles", "scatters", "boundary", "iterations", "capped", "kernel_ms"],
         "dmc_server_opts": ["memory_budget", "max_active", "epoch_flights", "drain_flights", "run"],
+        "dmc_tune_trial": ["block", "chunk", "refill_min", "lds_tally", "pilot", "ms", "flights_per_s"],
+        "dmc_tune_opts": ["sample_flights", "trial_cap", "use_cache", "trials", "max_trials", "n_trials",
+                          "from_cache"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for s, fields in structs.items():
@@ -111,6 +115,12 @@ def test_geometry_handles_without_device():
     g = b.Geometry(di.gray_slab().geometry)
     assert g.handle.value
     del g
+
+
+def test_autotune_validates_before_device_work():
+    best = b.dmc_run_opts()
+    assert b.lib().dmc_autotune(None, 0, None, None, C.byref(best)) == b.DMC_E_INVALID
+    assert b.lib().dmc_autotune(None, 1, None, None, None) == b.DMC_E_INVALID
 
 
 def test_debug_philox_rejects_null():

@@ -218,6 +218,28 @@ def test_batch_equals_solo_and_parameter_invariance():
             assert rel_diff(other.raw(j), ref.raw(j)) <= 1e-12, (params, j)
 
 
+def test_autotuner_choice_is_valid_cached_and_result_invariant():
+    """The tuner returns parameters from its search space, answers a repeated
+    signature from its cache, and the tuned launch gives the default launch's
+    FP64 tallies (only the order of FP64 additions may differ)."""
+    si = di.silicon_like()
+    mat = b.Material(si)
+    jobs = [di.slab_job(si, 80e-9, 20_000, seed=501, n_bins=20),
+            di.in_plane_film(40e-9, 0.5, 10_000, seed=502, material=si, kmax=40, n_hj=10),
+            di.pore_cell(70e-9, 0.3, 10_000, seed=503, material=si, kmax=40, n_hj=10),
+            small_spot_job()]
+    params, trials = b.autotune(jobs, material=mat, precision="fp64", sample_flights=2e6)
+    assert len(trials) >= 8 and all(t["ms"] > 0 and t["flights_per_s"] > 0 for t in trials)
+    assert params["block"] in (0, 256, 512, 1024) and params["chunk"] in (256, 1024, 4096)
+    assert params["refill_min"] in (1, 4, 16, 32) and params["lds_tally"] in (0, 1)
+    again, t2 = b.autotune(jobs, material=mat, precision="fp64", sample_flights=2e6)
+    assert again == params and t2 == []
+    ref = b.simulate(jobs, material=mat, precision="fp64")
+    tuned = b.simulate(jobs, material=mat, precision="fp64", **params)
+    for j in range(len(jobs)):
+        assert rel_diff(tuned.raw(j), ref.raw(j)) <= 1e-12, j
+
+
 def small_spot_job():
     from gpu_cases import small_spot
     return small_spot(n=2000, seed=406, grid=8, n_times=4)
