@@ -169,6 +169,12 @@ typedef struct {
     uint32_t *nscat_out;   /* optional device array (sum of the jobs' n_particles entries): the
                               scattering events of particle pid of job j are written at
                               (n_particles of jobs 0..j-1) + pid; not used by the server */
+    int32_t prio_flights;  /* persistent: a wave holding a particle past this many flights
+                              (4x, 16x as many) gets issue priority 1 (2, 3) on its SIMD,
+                              so that the few longest trajectories of a heavy-tailed job
+                              do not end the launch late; 0 = 65536, < 0 = off, at most
+                              2^27.  Changes timing only. */
+    int32_t pad0;
 } dmc_run_opts;
 
 /* Fills opts with the defaults (FP32 + FP64 tallies, persistent, auto parameters). */

@@ -56,7 +56,7 @@ class dmc_run_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("form", C.c_int32), ("stream", C.c_void_p), ("block", C.c_int32),
                 ("chunk", C.c_int32), ("refill_min", C.c_int32), ("lds_tally", C.c_int32),
                 ("grid_blocks", C.c_int32), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-                ("nscat_out", C.c_void_p)]
+                ("nscat_out", C.c_void_p), ("prio_flights", C.c_int32), ("pad0", C.c_int32)]
 
 
 class dmc_job(C.Structure):
@@ -360,7 +360,7 @@ def job_struct(job, material: Material, keep: list) -> dmc_job:
 
 
 def run_opts(precision="fp32", form="persistent", stream=None, block=0, chunk=0, refill_min=0, lds_tally=1,
-             grid_blocks=0, workspace=None, workspace_bytes=0, nscat_out=None) -> dmc_run_opts:
+             grid_blocks=0, workspace=None, workspace_bytes=0, nscat_out=None, prio_flights=0) -> dmc_run_opts:
     o = dmc_run_opts()
     dmc_run_opts_default(C.byref(o))
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
@@ -370,6 +370,7 @@ def run_opts(precision="fp32", form="persistent", stream=None, block=0, chunk=0,
     o.workspace = workspace
     o.workspace_bytes = workspace_bytes
     o.nscat_out = nscat_out
+    o.prio_flights = int(prio_flights)
     return o
 
 

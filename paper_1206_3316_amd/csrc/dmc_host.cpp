@@ -331,15 +331,17 @@ int device_cus()
 
 int kernel_spec(const JobDev *jobs, int n_jobs)
 {
-    bool slab = true, half = true;
+    bool slab = true, half = true, grad = true;
     for (int i = 0; i < n_jobs; ++i) {
         const JobDev &d = jobs[i];
         if (d.geom != GEOM_SLAB || d.src != SRC_WALLS || d.n_times > 0) slab = false;
         if (d.geom != GEOM_HALF || d.src != SRC_GAUSSIAN || d.n_times == 0 || d.n_bins > 0 || d.off_kappa >= 0 ||
             d.n_hj > 0)
             half = false;
+        if ((d.geom != GEOM_FILM && d.geom != GEOM_PORE) || d.src != SRC_GRADIENT || d.n_times > 0 || d.n_bins > 0)
+            grad = false;
     }
-    return slab ? (int)GEOM_SLAB : half ? (int)GEOM_HALF : (int)GEOM_ANY;
+    return slab ? (int)GEOM_SLAB : half ? (int)GEOM_HALF : grad ? (int)GEOM_GRAD : (int)GEOM_ANY;
 }
 
 dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, const std::vector<double> &times,
@@ -377,6 +379,9 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
     a.suspend_out = b.suspend_out;
     a.suspend_cap = b.suspend_cap;
     a.iter_cap = b.iter_cap ? std::min(b.iter_cap, kIterCap) : kIterCap;
+    a.prio_flights = o.prio_flights == 0 ? 65536u
+                     : o.prio_flights < 0            ? 0u
+                                                     : (uint32_t)std::min<int32_t>(o.prio_flights, 1 << 27);
     a.total += b.n_resume;
     if ((b.drain_iters || b.n_resume) && o.form != DMC_FORM_PERSISTENT)
         return fail(DMC_E_INVALID, "time-bounded launches need the persistent form");
@@ -413,6 +418,9 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
             }
         }
         a.lds_tally_doubles = lo;
+        a.bins_lds_all = 1;
+        for (auto &d : devs)
+            if (d.off_bins >= 0 && d.lds_bins < 0) a.bins_lds_all = 0;
         lds_bytes = ((tab + 15) & ~size_t(15)) + (size_t)lo * 8 + stats_lds;
         a.chunk = o.chunk > 0 ? o.chunk : 1024;
         a.refill_min = o.refill_min > 0 ? o.refill_min : 16;

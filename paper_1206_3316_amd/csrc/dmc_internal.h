@@ -16,7 +16,8 @@ constexpr int kMaxHj = 1024;
 constexpr int kLdsStatJobs = 64;         // per-job counters privatised in LDS up to this many jobs
 constexpr int kStats = 6;                // particles, scatters, boundary, iterations, capped, suspended
 
-enum Geom : int32_t { GEOM_SLAB = 0, GEOM_FILM = 1, GEOM_PORE = 2, GEOM_HALF = 3, GEOM_ANY = 9 };
+enum Geom : int32_t { GEOM_SLAB = 0, GEOM_FILM = 1, GEOM_PORE = 2, GEOM_HALF = 3, GEOM_GRAD = 8, GEOM_ANY = 9 };
+// GEOM_GRAD and GEOM_ANY only select kernel specialisations (see kernel_spec).
 enum Wall : int32_t { WALL_ISOTHERMAL = 0, WALL_ADIABATIC = 1, WALL_PERIODIC = 2 };
 enum Src : int32_t { SRC_WALLS = 0, SRC_GAUSSIAN = 1, SRC_GRADIENT = 2 };
 enum Form : int32_t { FORM_PLAIN = 0, FORM_PERSISTENT = 1 };
@@ -82,6 +83,7 @@ struct KArgs {
     int32_t lds_tally_doubles;      // LDS tally size; 0 = none
     int32_t lds_stats;              // 1: per-job counters in LDS
     int32_t kpad;                   // 2^gain_bits
+    int32_t bins_lds_all;           // 1: every job's bins are privatised in LDS
     // time-bounded launches (persistent form): queue indices [0, n_resume) resume
     // suspended particles; a wave that finds the queue empty runs at most
     // drain_iters more flights, then suspends its live particles
@@ -92,6 +94,8 @@ struct KArgs {
     Suspended *suspend_out;
     uint32_t suspend_cap;
     uint32_t iter_cap;              // flights after which a particle is stopped and counted as capped
+    uint32_t prio_flights;          // persistent: waves holding a particle past this many flights (4x,
+                                    // 16x) get SIMD issue priority 1 (2, 3); 0: off; at most 2^27
 };
 
 // Packed alias entry: column idx of a table with b index bits keeps idx iff
@@ -108,7 +112,9 @@ inline uint32_t pack_alias(uint32_t thresh, uint32_t alias, uint32_t idx, int bi
 
 // Launch entry points (dmc_kernels.hip).
 // spec: GEOM_SLAB (every job a steady wall-driven slab), GEOM_HALF (every job a
-// transient half-space Gaussian with snapshots only) or GEOM_ANY.
+// transient half-space Gaussian with snapshots only), GEOM_GRAD (every job a
+// film or pore cell under the gradient source, without bins or snapshots) or
+// GEOM_ANY.
 hipError_t launch_trajectories(const KArgs &a, int precision, int form, int spec, int block, int grid,
                                size_t lds_bytes, hipStream_t stream);
 hipError_t launch_fill(double *p, size_t n_doubles, unsigned long long *q, size_t n_u64, hipStream_t stream);

@@ -22,6 +22,8 @@
 //   G      GEOM_SLAB  cross-plane slab, wall sources, steady (dead components
 //                     eliminated)
 //          GEOM_HALF  half space, Gaussian initial condition, snapshots only
+//          GEOM_GRAD  in-plane films and pore cells under the gradient source of
+//                     Eq. (6), conductivity and H_j tallies only
 //          GEOM_ANY   every geometry and source, chosen per lane
 //
 // Random numbers: Philox4x32-10 (Salmon et al., SC'11) with key = seed and
@@ -154,9 +156,10 @@ struct Pr<double> {
 template <>
 struct Pr<float> {
     static constexpr float inf() { return __builtin_huge_valf(); }
-    // ((w >> 8) + 1/2) 2^-24: exact, strictly inside (0, 1), never denormal
-    __device__ static float u(uint32_t w) { return ((float)(w >> 8) + 0.5f) * 5.9604644775390625e-08f; }
-    // -tau ln u with the hardware log2 (u >= 2^-25, so no range fix-ups are needed)
+    // ((w >> 9) + 1/2) 2^-23 as one FMA: 24 significant bits, so exact; strictly
+    // inside (0, 1), never denormal
+    __device__ static float u(uint32_t w) { return fmaf((float)(w >> 9), 1.1920928955078125e-07f, 5.9604644775390625e-08f); }
+    // -tau ln u with the hardware log2 (u >= 2^-24, so no range fix-ups are needed)
     __device__ static float flight(float tau, uint32_t w) { return (tau * -0.693147182f) * __builtin_amdgcn_logf(u(w)); }
     __device__ static float sq(float x) { return __builtin_amdgcn_sqrtf(x); }
     // v_sin / v_cos take revolutions: sin(2 pi u) = sin_rev(u)
@@ -195,8 +198,10 @@ struct Lane {
     int64_t bg, hg;
     // accumulators
     double t, Lz, h;
-    int32_t cbin;
-    double c0, c1, c2;
+    int32_t cbin, dbin;     // bins of the two per-lane tally cache entries (-1: empty)
+    int32_t kbin;           // bin that holds the current position
+    double c0, c1, c2;      // entry A: the bin the particle is in
+    double d0, d1, d2;      // entry B: the bin it came from
     int32_t tcur;
     double tnext, tend;  // next snapshot time and final time (+inf when steady)
 };
@@ -246,6 +251,23 @@ __device__ __forceinline__ void tadd(const KArgs &a, const Shared &sh, int32_t l
         gadd(a.tally + (g_off + idx), v);
 }
 
+// Bin of coordinate c among nb bins of width 1/bpl, clamped to the slab.
+template <typename R>
+__device__ __forceinline__ int bin_of(R c, R bpl, int nb)
+{
+    int k = (int)floor(c * bpl);
+    return k < 0 ? 0 : (k > nb - 1 ? nb - 1 : k);
+}
+
+template <typename R>
+__device__ __forceinline__ void set_kbin(Lane<R> &p)
+{
+    if (p.n_bins > 0) p.kbin = bin_of((p.geom != GEOM_FILM) ? p.z : p.x, p.bpl, p.n_bins);
+}
+
+template <typename R, int FORM>
+__device__ __forceinline__ void bin_enter(Lane<R> &p, const KArgs &a, const Shared &sh, int32_t k);
+
 // ------------------------------------------------------------ emission ----
 
 // Lambertian direction about the inward normal sgn * e_axis (axis 0 or 2):
@@ -288,12 +310,12 @@ __device__ __forceinline__ void bind_job(Lane<R> &p, const JobDev &J, uint64_t p
     p.job = job;
     p.slot = J.stat_slot;
     p.batch = (int32_t)(pid % (uint64_t)J.n_batches);
-    p.geom = (G == GEOM_ANY) ? J.geom : G;
+    p.geom = (G == GEOM_ANY || G == GEOM_GRAD) ? J.geom : G;
     p.src = J.src;
-    p.n_bins = J.n_bins;
+    p.n_bins = (G == GEOM_HALF || G == GEOM_GRAD) ? 0 : J.n_bins;
     p.n_hj = J.n_hj;
     p.kmax = J.kmax;
-    p.n_times = J.n_times;
+    p.n_times = (G == GEOM_SLAB || G == GEOM_GRAD) ? 0 : J.n_times;
     p.len = (R)J.length;
     p.bpl = (R)J.bins_per_len;
     p.bw = (R)J.bin_width;
@@ -306,8 +328,9 @@ __device__ __forceinline__ void bind_job(Lane<R> &p, const JobDev &J, uint64_t p
         p.hl = J.lds_hj;
         p.hg = J.off_hj;
     }
-    p.cbin = -1;
+    p.cbin = p.dbin = -1;
     p.c0 = p.c1 = p.c2 = 0.0;
+    p.d0 = p.d1 = p.d2 = 0.0;
 }
 
 // Keeps the next snapshot time and the final time in registers.
@@ -338,7 +361,10 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
     const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
     const uint4 A = philox(plo, phi, 0u, TAG_EMIT_A, p.key0, p.key1);
     uint32_t m;
-    const int src = (G == GEOM_SLAB) ? (int)SRC_WALLS : (G == GEOM_HALF) ? (int)SRC_GAUSSIAN : p.src;
+    const int src = (G == GEOM_SLAB)   ? (int)SRC_WALLS
+                    : (G == GEOM_HALF) ? (int)SRC_GAUSSIAN
+                    : (G == GEOM_GRAD) ? (int)SRC_GRADIENT
+                                       : p.src;
     if (src == SRC_WALLS) {
         const uint32_t j = (J.n_src > 1) ? alias_draw(J.src_packed, 1, A.x) : 0u;
         const int wall = J.src_wall[j];
@@ -395,48 +421,86 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
         }
     }
     load_state(p, a, sh, m);
+    set_kbin(p);
+    p.cbin = (p.n_bins > 0) ? p.kbin : -1;  // cache entry A: the bin the particle is in
 }
 
 // ------------------------------------------------------------- scoring ----
 
+// Adds v to slot idx of the particle's bins: LDS when every job of the launch
+// has its bins privatised there (a launch-wide, wave-uniform test), else per
+// job (LDS or HBM).
+template <typename R, int FORM>
+__device__ __forceinline__ void bins_add(const Lane<R> &p, const KArgs &a, const Shared &sh, int32_t idx, double v)
+{
+    if (FORM == FORM_PERSISTENT && a.bins_lds_all)
+        atomicAdd(sh.ltally + (p.bl + idx), v);
+    else
+        tadd(a, sh, p.bl, p.bg, idx, v);
+}
+
+// Per-lane bin cache (persistent form): entry A holds the sums of the bin the
+// particle is in, entry B those of the bin it came from, so a particle that
+// walks back and forth across one bin edge adds to registers only; an entry is
+// added to the tallies when a third bin displaces it or the particle ends.
+template <typename R, int FORM>
+__device__ __forceinline__ void flush_entry(Lane<R> &p, const KArgs &a, const Shared &sh, int32_t bin, double &s0,
+                                            double &s1, double &s2)
+{
+    if (bin < 0) return;
+    bins_add<R, FORM>(p, a, sh, bin, s0);
+    bins_add<R, FORM>(p, a, sh, bin + p.n_bins, s1);
+    bins_add<R, FORM>(p, a, sh, bin + 2 * p.n_bins, s2);
+    s0 = s1 = s2 = 0.0;
+}
+
 template <typename R, int FORM>
 __device__ __forceinline__ void bin_flush(Lane<R> &p, const KArgs &a, const Shared &sh)
 {
-    if (p.cbin < 0) return;
-    tadd(a, sh, p.bl, p.bg, p.cbin, p.c0);
-    tadd(a, sh, p.bl, p.bg, p.cbin + p.n_bins, p.c1);
-    tadd(a, sh, p.bl, p.bg, p.cbin + 2 * p.n_bins, p.c2);
-    p.cbin = -1;
-    p.c0 = p.c1 = p.c2 = 0.0;
+    if (FORM != FORM_PERSISTENT) return;  // the plain form adds every contribution directly
+    flush_entry<R, FORM>(p, a, sh, p.cbin, p.c0, p.c1, p.c2);
+    flush_entry<R, FORM>(p, a, sh, p.dbin, p.d0, p.d1, p.d2);
+    p.cbin = p.dbin = -1;
+}
+
+// Makes entry A the one of bin k (the particle's new bin).
+template <typename R, int FORM>
+__device__ __forceinline__ void bin_enter(Lane<R> &p, const KArgs &a, const Shared &sh, int32_t k)
+{
+    if (k == p.cbin) return;
+    int32_t tb = p.cbin;
+    p.cbin = p.dbin;
+    p.dbin = tb;
+    double t0 = p.c0, t1 = p.c1, t2 = p.c2;
+    p.c0 = p.d0;
+    p.c1 = p.d1;
+    p.c2 = p.d2;
+    p.d0 = t0;
+    p.d1 = t1;
+    p.d2 = t2;
+    if (p.cbin != k) {
+        flush_entry<R, FORM>(p, a, sh, p.cbin, p.c0, p.c1, p.c2);
+        p.cbin = k;
+    }
 }
 
 // Time t spent in bin k: TIME += s t, PTIME += s t / tau, DISP += s v Omega_z t.
+// cached: k is the bin of entry A (persistent form); otherwise a direct add.
 template <typename R, int FORM>
-__device__ __forceinline__ void bin_add(Lane<R> &p, const KArgs &a, const Shared &sh, int k, R t, R vz, bool cache)
+__device__ __forceinline__ void bin_add(Lane<R> &p, const KArgs &a, const Shared &sh, int k, R t, R vz, bool cached)
 {
     const double d0 = (double)(p.s * t);
     const double d1 = (double)(p.s * Pr<R>::ptime(t, p.tau, p.itau));
     const double d2 = (double)(p.s * vz * t);
-    if (FORM == FORM_PERSISTENT && cache) {
-        if (k != p.cbin) {
-            bin_flush<R, FORM>(p, a, sh);
-            p.cbin = k;
-        }
+    if (FORM == FORM_PERSISTENT && cached) {
         p.c0 += d0;
         p.c1 += d1;
         p.c2 += d2;
     } else {
-        tadd(a, sh, p.bl, p.bg, k, d0);
-        tadd(a, sh, p.bl, p.bg, k + p.n_bins, d1);
-        tadd(a, sh, p.bl, p.bg, k + 2 * p.n_bins, d2);
+        bins_add<R, FORM>(p, a, sh, k, d0);
+        bins_add<R, FORM>(p, a, sh, k + p.n_bins, d1);
+        bins_add<R, FORM>(p, a, sh, k + 2 * p.n_bins, d2);
     }
-}
-
-template <typename R>
-__device__ __forceinline__ int bin_of(R c, R bpl, int nb)
-{
-    int k = (int)floor(c * bpl);
-    return k < 0 ? 0 : (k > nb - 1 ? nb - 1 : k);
 }
 
 // Track-length scoring of one segment into the 1-D bins (slab: z, film: x).
@@ -448,35 +512,33 @@ __device__ void score_bins(Lane<R> &p, const KArgs &a, const Shared &sh, const J
     const R wa = p.v * (zax ? p.oz : p.ox);
     const R vz = p.v * p.oz;
     const int nb = p.n_bins;
-    const int ka = bin_of(ca, p.bpl, nb);
+    const int ka = p.kbin;  // bin_of(ca): the end bin of the previous segment
+    constexpr bool C = (FORM == FORM_PERSISTENT);
     if (wa == (R)0) {
-        bin_add<R, FORM>(p, a, sh, ka, seg, vz, true);
+        bin_add<R, FORM>(p, a, sh, ka, seg, vz, C);
         return;
     }
+    // the position update of the step computes exactly cb, so kb is the next
+    // segment's start bin (a boundary interaction recomputes it)
     const R cb = ca + wa * seg;
     const int kb = bin_of(cb, p.bpl, nb);
+    p.kbin = kb;
     if (ka == kb) {
-        bin_add<R, FORM>(p, a, sh, ka, seg, vz, true);
+        bin_add<R, FORM>(p, a, sh, ka, seg, vz, C);
         return;
     }
     const R aw = fabs(wa);
     const R inv = Pr<R>::div((R)1, aw);
     const R bw = p.bw;
-    if (wa > (R)0) {
-        const R t0 = fmax(((R)(ka + 1) * bw - ca) * inv, (R)0);
-        bin_add<R, FORM>(p, a, sh, ka, t0, vz, true);
-        const R tin = bw * inv;
-        for (int k = ka + 1; k < kb; ++k) bin_add<R, FORM>(p, a, sh, k, tin, vz, false);
-        const R t1 = fmax((cb - (R)kb * bw) * inv, (R)0);
-        bin_add<R, FORM>(p, a, sh, kb, t1, vz, true);
-    } else {
-        const R t0 = fmax((ca - (R)ka * bw) * inv, (R)0);
-        bin_add<R, FORM>(p, a, sh, ka, t0, vz, true);
-        const R tin = bw * inv;
-        for (int k = ka - 1; k > kb; --k) bin_add<R, FORM>(p, a, sh, k, tin, vz, false);
-        const R t1 = fmax(((R)(kb + 1) * bw - cb) * inv, (R)0);
-        bin_add<R, FORM>(p, a, sh, kb, t1, vz, true);
-    }
+    const bool up = wa > (R)0;
+    const R t0 = up ? fmax(((R)(ka + 1) * bw - ca) * inv, (R)0) : fmax((ca - (R)ka * bw) * inv, (R)0);
+    const R t1 = up ? fmax((cb - (R)kb * bw) * inv, (R)0) : fmax(((R)(kb + 1) * bw - cb) * inv, (R)0);
+    bin_add<R, FORM>(p, a, sh, ka, t0, vz, C);
+    const R tin = bw * inv;
+    const int step = up ? 1 : -1;
+    for (int k = ka + step; k != kb; k += step) bin_add<R, FORM>(p, a, sh, k, tin, vz, false);
+    if (C) bin_enter<R, FORM>(p, a, sh, kb);
+    bin_add<R, FORM>(p, a, sh, kb, t1, vz, C);
 }
 
 // Snapshot estimator (Eq. (3)) at every sample time in [t, t + seg).
@@ -696,6 +758,8 @@ __device__ void resume(Lane<R> &p, const KArgs &a, const Shared &sh, uint32_t i)
     set_times(p, a, J);
     p.s = (R)S.sign;
     load_state(p, a, sh, S.m);
+    set_kbin(p);
+    p.cbin = (p.n_bins > 0) ? p.kbin : -1;
 }
 
 // ---------------------------------------------------------------- finish ----
@@ -727,28 +791,41 @@ __device__ void finish(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDe
 
 // ------------------------------------------------------------------ step ----
 
+// The STEP block of flight k.  When every active lane of the wave carries the
+// same key (the usual case: a wave's particles come from one job), the key
+// schedule runs once on the scalar unit instead of once per lane.
+template <typename R>
+__device__ __forceinline__ uint4 philox_step(const Lane<R> &p)
+{
+    const uint32_t c0 = (uint32_t)p.pid, c1 = (uint32_t)(p.pid >> 32);
+    const uint32_t k0 = __builtin_amdgcn_readfirstlane(p.key0);
+    const uint32_t k1 = __builtin_amdgcn_readfirstlane(p.key1);
+    if (__ballot(p.key0 != k0 || p.key1 != k1) == 0ull) return philox(c0, c1, p.k, TAG_STEP, k0, k1);
+    return philox(c0, c1, p.k, TAG_STEP, p.key0, p.key1);
+}
+
 // One iteration of steps II-VI.  Returns 0 if the particle goes on, 1 if it
 // ended, 2 if it hit the flight cap.
 template <typename R, int FORM, int G>
 __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J)
 {
-    const uint4 w = philox((uint32_t)p.pid, (uint32_t)(p.pid >> 32), p.k, TAG_STEP, p.key0, p.key1);
+    const uint4 w = philox_step(p);
     ++p.k;
     const R dt = Pr<R>::flight(p.tau, w.x);                           // step II
     int32_t surf;
-    const int geom = (G == GEOM_ANY) ? p.geom : G;
+    const int geom = (G == GEOM_ANY || G == GEOM_GRAD) ? p.geom : G;
     const R tb = search(p, J, geom, surf);                           // step III
     const bool boundary = (tb <= dt);
     const R seg = boundary ? tb : dt;
     // step V: sample the segment
-    if (G != GEOM_HALF && p.n_bins > 0) score_bins<R, FORM>(p, a, sh, J, seg);
-    const bool gradient = (G == GEOM_ANY) && (p.src == SRC_GRADIENT);
+    if (p.n_bins > 0) score_bins<R, FORM>(p, a, sh, J, seg);
+    const bool gradient = (G == GEOM_GRAD) || ((G == GEOM_ANY) && (p.src == SRC_GRADIENT));
     if (gradient) {
         const double dz = (double)(p.s * p.v * p.oz * seg);
         p.Lz += dz;
         if (p.nscat < (uint32_t)p.n_hj) p.h += dz;
     }
-    if (G != GEOM_SLAB) {
+    if (G == GEOM_ANY || G == GEOM_HALF) {
         const double tb_abs = p.t + (double)seg;
         if (p.tnext < tb_abs) score_snapshots(p, a, J, (double)seg);
         if (tb_abs > p.tend) return 1;  // step VI
@@ -772,6 +849,10 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
         }
         ++p.nbound;
         if (interact(p, J, surf, w)) return 1;
+        if (p.n_bins > 0) {
+            set_kbin(p);  // a periodic face moves the particle to the other end
+            if (FORM == FORM_PERSISTENT) bin_enter<R, FORM>(p, a, sh, p.kbin);
+        }
     } else {                                                          // step IVb
         const uint32_t m = alias_draw(sh.gain, a.gain_bits, w.y);
         load_state(p, a, sh, m);
@@ -915,7 +996,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
     int job = 0;
     uint64_t pool_cur = 0, pool_end = 0;  // wave-uniform slice of the queue
     bool qdry = false;  // the global queue has handed out every index (wave-uniform)
-    uint32_t drain = 0, poll = 0;
+    uint32_t drain = 0, poll = 0, iter = 0;
     for (;;) {
         // refill free lanes from this wave's chunk, taking a new chunk from the
         // queue (one atomic per wave) when it is used up
@@ -988,6 +1069,22 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                 }
                 break;
             }
+        }
+        if (a.prio_flights && ((++iter) & 63u) == 0u) {
+            // trajectory lengths are heavy-tailed and a launch ends with its longest
+            // particle, whose flights are otherwise paced by a fair share of its
+            // SIMD: waves get issue priority by the age of their oldest particle
+            // (past prio_flights, 4x and 16x that), so the longest-running
+            // trajectories advance first; their other lanes keep refilling as usual
+            const uint32_t t1 = a.prio_flights;
+            if (__ballot(alive && p.k >= 16u * t1))
+                __builtin_amdgcn_s_setprio(3);
+            else if (__ballot(alive && p.k >= 4u * t1))
+                __builtin_amdgcn_s_setprio(2);
+            else if (__ballot(alive && p.k >= t1))
+                __builtin_amdgcn_s_setprio(1);
+            else
+                __builtin_amdgcn_s_setprio(0);
         }
         if (alive) {
             const JobDev &J = a.jobs[p.job];
@@ -1064,6 +1161,7 @@ const void *pick_geom(int spec, int form, bool bounded)
 {
     if (spec == GEOM_SLAB) return kernel_ptr<R, GEOM_SLAB>(form, bounded);
     if (spec == GEOM_HALF) return kernel_ptr<R, GEOM_HALF>(form, bounded);
+    if (spec == GEOM_GRAD) return kernel_ptr<R, GEOM_GRAD>(form, bounded);
     return kernel_ptr<R, GEOM_ANY>(form, bounded);
 }
 

@@ -47,7 +47,7 @@ def layout_probe(tmp_path_factory):
         "dmc_source": ["kind", "dT", "radius", "gradient"],
         "dmc_tally_desc": ["n_bins", "n_batches", "kmax", "n_hj", "grid", "grid_lo", "grid_hi"],
         "dmc_run_opts": ["precision", "form", "stream", "block", "chunk", "refill_min", "lds_tally", "grid_blocks",
-                         "workspace", "workspace_bytes", "nscat_out"],
+                         "workspace", "workspace_bytes", "nscat_out", "prio_flights"],
         "dmc_job": ["material", "geometry", "source", "tally", "n_particles", "seed", "times", "n_times",
                     "first_particle"],
         "dmc_stats": ["particles", "scatters", "boundary", "iterations", "capped", "kernel_ms"],
