@@ -33,24 +33,27 @@ sys.path.insert(0, ROOT)
 # Algorithmic VALU work of one flight of the cross-plane slab path, counted in
 # full-rate VALU issue slots per lane (the MI355X issues 64 lane-slots per CU
 # per clock).  Instruction costs on gfx950 were measured with a throughput
-# probe: a Philox4x32-10 block (20 32x32->64 multiply-adds, 20 xors, 18 key
-# additions) takes 57 lane-slots; v_log_f32 takes 2.
+# probe: a Philox4x32-10 block (20 32x32->64 multiply-adds and the xors, with
+# the key schedule on the scalar unit since a wave's particles share a seed)
+# takes 57 lane-slots; v_log_f32 takes 2.
 #   Philox4x32-10 block                                                  57
-#   two word -> uniform conversions (shift, convert, add 1/2, scale)      8
+#   two word -> uniform conversions (shift, convert, one FMA each)          6
 #   -ln u: log2 (2) and two multiplies; mu = 2u - 1 (2)                     6
 #   wall distance and reciprocal, hit test, segment select                 8
 #   position update                                                        2
-#   two bin indices (scale, floor, convert, 2 clamps) and 2 compares       12
+#   end-of-segment bin index (scale, floor, convert, 2 clamps), compare     6
 #   three FP64 tally accumulations (5 FP32 products, 3 converts, 3 adds)   11
 #   gain alias draw (shift, mask, compare, select) + state fetch address    6
 #   flight / scatter counters, truncation and cap tests                    5
-# plus 2 for the sign and select logic of the boundary/scatter outcome.
-OPS_PER_FLIGHT = 117
+# plus 2 for the sign and select logic of the boundary/scatter outcome.  The
+# start bin of a segment is the end bin of the previous one, so one bin index
+# per flight is the minimum.
+OPS_PER_FLIGHT = 109
 # HBM traffic of one launch of the timed workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs (profiles/), scaled by the same counters' reading for a plain
 # device copy of known size (bench.py --copy-probe); valid only for the kernel
 # source it was measured on.
-TRAFFIC = {"kernel_sha1": "7f61830f418821ca350fc7a39e81ae3b689132c6", "bytes": 33842586}  # profiles/persistent_kernel_slab_12films_counters.md
+TRAFFIC = {"kernel_sha1": "962feecbfbcfdbea76bcc3b3d03b64029970d883", "bytes": 61969504}  # profiles/persistent_kernel_slab_12films_counters.md
 CU, LANES_PER_CU_CLK, CLOCK = 256, 64, 2.4e9
 PEAK_LANE_OPS = CU * LANES_PER_CU_CLK * CLOCK  # 3.93e13 full-rate VALU lane-ops/s
 
@@ -86,15 +89,18 @@ def cpu_baseline(jobs, target_s=15.0):
             "sample": f"first {n} particles of each of the 12 films ({ev} scattering events, {dt:.1f} s)"}
 
 
-def launch_params(jobs, mat, precision="fp32", stream=None, overrides=None):
+def launch_params(jobs, mat, precision="fp32", stream=None, overrides=None, tune=True):
     """Launch parameters of the timed configuration: the library's autotuner on
-    this batch (cached per process and batch signature), then any explicit
-    non-zero overrides."""
+    this batch (cached per process and batch signature), or the library's
+    defaults when tune is False, then any explicit non-zero overrides."""
     from paper_1206_3316_amd import binding as b
 
-    params, trials = b.autotune(jobs, material=mat, precision=precision, stream=stream)
-    if trials:
-        launch_params.trials = trials
+    if tune:
+        params, trials = b.autotune(jobs, material=mat, precision=precision, stream=stream)
+        if trials:
+            launch_params.trials = trials
+    else:
+        params = {"block": 0, "chunk": 0, "refill_min": 0, "lds_tally": 1}
     for k, v in (overrides or {}).items():
         if v:
             params[k] = v
@@ -200,6 +206,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="queue chunk (0: autotuned)")
     ap.add_argument("--refill-min", type=int, default=0, help="refill threshold (0: autotuned)")
     ap.add_argument("--block", type=int, default=0, help="workgroup size (0: autotuned)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (library defaults plus --block/--chunk/--refill-min); "
+                         "profiles use it so that only the timed launches are traced")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=200)
@@ -228,7 +237,8 @@ def main():
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     t_tune = time.perf_counter()
     params = launch_params(jobs, mat, stream=stream,
-                           overrides={"chunk": args.chunk, "refill_min": args.refill_min, "block": args.block})
+                           overrides={"chunk": args.chunk, "refill_min": args.refill_min, "block": args.block},
+                           tune=not args.no_tune)
     log(f"launch parameters {params} (autotuner {time.perf_counter() - t_tune:.1f} s, "
         f"{len(getattr(launch_params, 'trials', []))} trials)")
 
