@@ -149,6 +149,7 @@ struct Pr<double> {
     __device__ static double div(double a, double b) { return a / b; }
     __device__ static double ptime(double t, double tau, double) { return t / tau; }
     __device__ static double lg(double x) { return det_log(x); }
+    __device__ static double mu(uint32_t w) { return 2.0 * u(w) - 1.0; }
     // FP64 keeps the reference's arithmetic unchanged
     __device__ static double nonneg(double t) { return t; }
 };
@@ -172,6 +173,8 @@ struct Pr<float> {
     __device__ static float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     __device__ static float ptime(float t, float, float itau) { return t * itau; }
     __device__ static float lg(float x) { return __builtin_amdgcn_logf(x) * 0.693147182f; }
+    // 2u - 1 is exact for these u, so one FMA gives the same value
+    __device__ static float mu(uint32_t w) { return fmaf(2.0f, u(w), -1.0f); }
     // a position rounded just past a wall must not yield a negative flight time
     __device__ static float nonneg(float t) { return fmaxf(t, 0.0f); }
 };
@@ -293,7 +296,7 @@ __device__ __forceinline__ void lambertian_plane(Lane<R> &p, int axis, R sgn, ui
 template <typename R>
 __device__ __forceinline__ void isotropic(Lane<R> &p, uint32_t w2, uint32_t w3)
 {
-    const R mu = (R)2 * Pr<R>::u(w2) - (R)1;
+    const R mu = Pr<R>::mu(w2);
     R c, s;
     Pr<R>::cs(w3, c, s);
     const R st = Pr<R>::sq((R)1 - mu * mu);
@@ -504,6 +507,10 @@ __device__ __forceinline__ void bin_add(Lane<R> &p, const KArgs &a, const Shared
 }
 
 // Track-length scoring of one segment into the 1-D bins (slab: z, film: x).
+// Persistent form: the whole segment is added to the cache entry of the
+// current bin (every lane does the same work); a segment that leaves the bin
+// then moves the part beyond the bin's edge to the bins it reaches.  The plain
+// form adds each bin's part directly.
 template <typename R, int FORM>
 __device__ void score_bins(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, R seg)
 {
@@ -513,32 +520,59 @@ __device__ void score_bins(Lane<R> &p, const KArgs &a, const Shared &sh, const J
     const R vz = p.v * p.oz;
     const int nb = p.n_bins;
     const int ka = p.kbin;  // bin_of(ca): the end bin of the previous segment
-    constexpr bool C = (FORM == FORM_PERSISTENT);
-    if (wa == (R)0) {
-        bin_add<R, FORM>(p, a, sh, ka, seg, vz, C);
-        return;
+    if constexpr (FORM == FORM_PERSISTENT) {
+        bin_add<R, FORM>(p, a, sh, ka, seg, vz, true);
+        if (wa == (R)0) return;
+        // the position update of the step computes exactly cb, so kb is the next
+        // segment's start bin (a boundary interaction recomputes it)
+        const R cb = ca + wa * seg;
+        const int kb = bin_of(cb, p.bpl, nb);
+        p.kbin = kb;
+        if (ka == kb) return;
+        const R inv = Pr<R>::div((R)1, fabs(wa));
+        const R bw = p.bw;
+        const bool up = wa > (R)0;
+        const R t1 = up ? fmax((cb - (R)kb * bw) * inv, (R)0) : fmax(((R)(kb + 1) * bw - cb) * inv, (R)0);
+        const int nin = (up ? kb - ka : ka - kb) - 1;  // bins crossed from edge to edge
+        if (nin > 0) {
+            const R tin = bw * inv;
+            const int step = up ? 1 : -1;
+            for (int k = ka + step; k != kb; k += step) bin_add<R, FORM>(p, a, sh, k, tin, vz, false);
+            bin_add<R, FORM>(p, a, sh, ka, -((R)nin * tin), vz, true);
+        }
+        const double e0 = (double)(p.s * t1);
+        const double e1 = (double)(p.s * Pr<R>::ptime(t1, p.tau, p.itau));
+        const double e2 = (double)(p.s * vz * t1);
+        p.c0 -= e0;
+        p.c1 -= e1;
+        p.c2 -= e2;
+        bin_enter<R, FORM>(p, a, sh, kb);
+        p.c0 += e0;
+        p.c1 += e1;
+        p.c2 += e2;
+    } else {
+        if (wa == (R)0) {
+            bin_add<R, FORM>(p, a, sh, ka, seg, vz, false);
+            return;
+        }
+        const R cb = ca + wa * seg;
+        const int kb = bin_of(cb, p.bpl, nb);
+        p.kbin = kb;
+        if (ka == kb) {
+            bin_add<R, FORM>(p, a, sh, ka, seg, vz, false);
+            return;
+        }
+        const R inv = Pr<R>::div((R)1, fabs(wa));
+        const R bw = p.bw;
+        const bool up = wa > (R)0;
+        const R t0 = up ? fmax(((R)(ka + 1) * bw - ca) * inv, (R)0) : fmax((ca - (R)ka * bw) * inv, (R)0);
+        const R t1 = up ? fmax((cb - (R)kb * bw) * inv, (R)0) : fmax(((R)(kb + 1) * bw - cb) * inv, (R)0);
+        bin_add<R, FORM>(p, a, sh, ka, t0, vz, false);
+        const R tin = bw * inv;
+        const int step = up ? 1 : -1;
+        for (int k = ka + step; k != kb; k += step) bin_add<R, FORM>(p, a, sh, k, tin, vz, false);
+        bin_add<R, FORM>(p, a, sh, kb, t1, vz, false);
     }
-    // the position update of the step computes exactly cb, so kb is the next
-    // segment's start bin (a boundary interaction recomputes it)
-    const R cb = ca + wa * seg;
-    const int kb = bin_of(cb, p.bpl, nb);
-    p.kbin = kb;
-    if (ka == kb) {
-        bin_add<R, FORM>(p, a, sh, ka, seg, vz, C);
-        return;
-    }
-    const R aw = fabs(wa);
-    const R inv = Pr<R>::div((R)1, aw);
-    const R bw = p.bw;
-    const bool up = wa > (R)0;
-    const R t0 = up ? fmax(((R)(ka + 1) * bw - ca) * inv, (R)0) : fmax((ca - (R)ka * bw) * inv, (R)0);
-    const R t1 = up ? fmax((cb - (R)kb * bw) * inv, (R)0) : fmax(((R)(kb + 1) * bw - cb) * inv, (R)0);
-    bin_add<R, FORM>(p, a, sh, ka, t0, vz, C);
-    const R tin = bw * inv;
-    const int step = up ? 1 : -1;
-    for (int k = ka + step; k != kb; k += step) bin_add<R, FORM>(p, a, sh, k, tin, vz, false);
-    if (C) bin_enter<R, FORM>(p, a, sh, kb);
-    bin_add<R, FORM>(p, a, sh, kb, t1, vz, C);
 }
 
 // Snapshot estimator (Eq. (3)) at every sample time in [t, t + seg).
