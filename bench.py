@@ -107,6 +107,31 @@ def launch_params(jobs, mat, precision="fp32", stream=None, overrides=None, tune
     return params
 
 
+def other_workloads(b, di, mat, mat_in, stream):
+    """One autotuned launch each of the transient heated spot (1e9 particles,
+    64^3 grid x 50 times) and of the 64 batched nanostructures (1e6-1e8
+    particles each, K_max = 40), after the tuner's trials have loaded the
+    kernels.  Reported beside the headline, not in it."""
+    res = {}
+    for name, jobs in (("heated_spot_1e9_64cube_50times", [di.heated_spot(material=mat_in)]),
+                       ("nanostructures_64_instances", di.batched_nanostructures(material=mat_in))):
+        t0 = time.perf_counter()
+        params = launch_params(jobs, mat, stream=stream)
+        tune_s = time.perf_counter() - t0
+        r = b.simulate(jobs, material=mat, stream=stream, **params)
+        st = [r.stats(i) for i in range(len(jobs))]
+        ms = st[0].kernel_ms
+        sc = sum(s.scatters for s in st)
+        fl = sum(s.iterations for s in st)
+        parts = sum(s.particles for s in st)
+        res[name] = {"scattering_events_per_s": sc / (ms / 1e3), "particles_per_s": parts / (ms / 1e3),
+                     "flights_per_s": fl / (ms / 1e3), "kernel_ms": ms, "particles": parts, "scattering_events": sc,
+                     "capped": sum(s.capped for s in st), "launch": params, "autotune_s": tune_s}
+        log(f"{name}: {sc:.3e} scatters in {ms:.1f} ms ({sc / (ms / 1e3):.3e} /s), params {params}")
+        r.close()
+    return res
+
+
 def flights_per_particle(job, sums):
     C_tot, G_tau, G_v = sums
     if job.source.kind == "walls":
@@ -116,13 +141,33 @@ def flights_per_particle(job, sums):
     return 1.5 * job.tally.kmax + 1.0
 
 
-def serve(b, di, torch, mat, mat_in, stream, capacity, n_requests, args):
+def mix_capacity(b, di, mat, reqs, stream, n_sample=48, n_cap=2_000_000):
+    """Flights/s of the request mix itself: the first n_sample requests, each cut
+    to at most n_cap particles, in one persistent launch (the mix runs the
+    generic kernel, slower than the headline's slab kernel)."""
+    import copy
+    sample = []
+    for _, j in reqs[:n_sample]:
+        c = copy.copy(j)
+        c.n_particles = min(j.n_particles, n_cap)
+        sample.append(c)
+    r = b.simulate(sample, material=mat, stream=stream)
+    st = [r.stats(i) for i in range(len(sample))]
+    fl = sum(s.iterations for s in st)
+    r.close()
+    return fl / (st[0].kernel_ms / 1e3)
+
+
+def serve(b, di, torch, mat, mat_in, stream, n_requests, args):
     """Poisson stream of mixed requests (films, heated spots, pore cells) on the
-    continuous-batching server at 0.8 x measured capacity; p50/p99 latency."""
+    continuous-batching server at 0.8 x the mix's measured capacity; p50/p99
+    latency."""
     _, sums = mat.info()
     reqs = di.serving_stream(n_requests, material=mat_in)
     work = [j.n_particles * flights_per_particle(j, sums) for _, j in reqs]
+    capacity = mix_capacity(b, di, mat, reqs, stream)
     rate = 0.8 * capacity / (sum(work) / len(work))
+    log(f"serving: mix capacity {capacity:.3e} flights/s, arrival rate {rate:.2f} requests/s")
     arrivals = di.poisson_arrivals(n_requests, rate)
     free, _ = torch.cuda.mem_get_info()
     budget = int(min(0.8 * free, 64 << 30))
@@ -173,7 +218,7 @@ def serve(b, di, torch, mat, mat_in, stream, capacity, n_requests, args):
     srv.close()
     lat_s = sorted(lat)
     pct = lambda p: lat_s[min(len(lat_s) - 1, int(round(p / 100.0 * (len(lat_s) - 1))))]
-    return {"requests": n_requests, "arrival_rate_per_s": rate, "p50_latency_s": pct(50), "p99_latency_s": pct(99),
+    return {"requests": n_requests, "arrival_rate_per_s": rate, "mix_capacity_flights_per_s": capacity, "p50_latency_s": pct(50), "p99_latency_s": pct(99),
             "scattering_events_per_s": scat / wall, "wall_s": wall, "epochs": epochs,
             "mean_epoch_ms": 1e3 * epoch_s / max(epochs, 1),
             "mix_vs_alone_max_rel_diff": getattr(serve, "mix_vs_alone", None),
@@ -215,6 +260,8 @@ def main():
     ap.add_argument("--epoch-flights", type=float, default=2e10)
     ap.add_argument("--serve-max-s", type=float, default=90.0, help="stop admitting requests after this long")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the single-launch measurements of the heated spot and the batched nanostructures")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
@@ -293,9 +340,11 @@ def main():
                              "persistent_same_sample_events_per_s": sq.scatters / (sq.kernel_ms / 1e3)}
         out["vs_plain"] = value / plain_rate
     if args.serve_requests > 0:
-        out["serving"] = serve(b, di, torch, mat, mat_in, stream, value, args.serve_requests, args)
+        out["serving"] = serve(b, di, torch, mat, mat_in, stream, args.serve_requests, args)
         out["p50_latency_s"] = out["serving"]["p50_latency_s"]
         out["p99_latency_s"] = out["serving"]["p99_latency_s"]
+    if not args.no_extra:
+        out["other_workloads"] = other_workloads(b, di, mat, mat_in, stream)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(jobs)
     print(json.dumps(out))

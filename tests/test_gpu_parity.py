@@ -139,7 +139,13 @@ def _assert_stat_close(name, q, got, got_se, ref, ref_se, scale=None, rel=1e-3):
     comb = np.sqrt(np.atleast_1d(got_se) ** 2 + np.atleast_1d(ref_se) ** 2)
     sc = float(np.abs(ref).max()) if scale is None else scale
     tol = np.maximum(3.0 * comb, rel * sc)
-    bad = np.abs(got - ref) > tol
+    diff = np.abs(got - ref)
+    # the FP32 production error against the FP64 oracle, per tallied quantity
+    with np.errstate(divide="ignore", invalid="ignore"):
+        in_se = np.where(comb > 0, diff / comb, 0.0)
+    print(f"fp32-vs-oracle {name} {q}: max |diff| / scale = {diff.max() / sc:.2e}, "
+          f"max |diff| / combined SE = {in_se.max():.2f} over {diff.shape[0]} values", flush=True)
+    bad = diff > tol
     assert not bad.any(), (name, q, got[bad], ref[bad], tol[bad])
 
 
