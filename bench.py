@@ -42,13 +42,15 @@ sys.path.insert(0, ROOT)
 #   wall distance and reciprocal, hit test, segment select                 8
 #   position update                                                        2
 #   end-of-segment bin index (scale, floor, convert, 2 clamps), compare     6
-#   three FP64 tally accumulations (5 FP32 products, 3 converts, 3 adds)   11
+#   two FP64 tally accumulations, time and time/tau (3 FP32 products,
+#   2 converts, 2 adds); the displacement telescopes along the path          7
 #   gain alias draw (shift, mask, compare, select) + state fetch address    6
 #   flight / scatter counters, truncation and cap tests                    5
 # plus 2 for the sign and select logic of the boundary/scatter outcome.  The
 # start bin of a segment is the end bin of the previous one, so one bin index
-# per flight is the minimum.
-OPS_PER_FLIGHT = 109
+# per flight is the minimum; the signed length through a bin depends only on a
+# trajectory's end points, so it costs nothing per flight.
+OPS_PER_FLIGHT = 105
 # HBM traffic of one launch of the timed workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs (profiles/), scaled by the same counters' reading for a plain
 # device copy of known size (bench.py --copy-probe); valid only for the kernel

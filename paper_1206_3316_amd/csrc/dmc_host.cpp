@@ -197,7 +197,9 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
     d.n_hj = t.n_hj;
     d.n_times = jb.n_times;
     d.lds_bins = d.lds_kappa = d.lds_hj = -1;
-    d.off_bins = d.off_kappa = d.off_hj = d.off_snap = d.off_snap_abs = -1;
+    d.off_bins = d.off_kappa = d.off_hj = d.off_snap = d.off_snap_abs = d.off_dispx = -1;
+    d.lds_dispx = -1;
+    d.disp_tel = 0;
     if ((g.kind == DMC_GEOM_SLAB_Z || g.kind == DMC_GEOM_FILM_X) && t.n_bins > 0) {
         d.bins_per_len = (double)t.n_bins / g.length;
         d.bin_width = g.length / (double)t.n_bins;
@@ -292,15 +294,32 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
         // sum |s| = |sum s| per cell: the device skips that second atomic
         d.snap_abs_on = (s.kind == DMC_SRC_GAUSSIAN) ? 0 : 1;
     }
+    if (t.n_bins > 0) {  // last: the visible block stays contiguous
+        // hidden: not part of the raw block a caller reads (the host folds it into
+        // the displacement bins when the launch used it)
+        d.off_dispx = o;
+        o += (int64_t)t.n_batches;
+        h.hidden = t.n_batches;
+    }
     h.size = o;
     return DMC_OK;
 }
 
 void complete_tally(const JobDev &d, double *block)
 {
-    if (d.off_snap_abs < 0 || d.snap_abs_on) return;
-    const int64_t n = (int64_t)d.n_times * (d.ncell + 1);
-    for (int64_t i = 0; i < n; ++i) block[d.off_snap_abs + i] = std::fabs(block[d.off_snap + i]);
+    if (d.off_snap_abs >= 0 && !d.snap_abs_on) {
+        const int64_t n = (int64_t)d.n_times * (d.ncell + 1);
+        for (int64_t i = 0; i < n; ++i) block[d.off_snap_abs + i] = std::fabs(block[d.off_snap + i]);
+    }
+    if (d.disp_tel && d.off_dispx >= 0 && d.off_bins >= 0) {
+        // every net transmission carries one bin width through every bin
+        for (int b = 0; b < d.n_batches; ++b) {
+            const double x = d.bin_width * block[d.off_dispx + b];
+            double *disp = block + d.off_bins + ((int64_t)b * 3 + 2) * d.n_bins;
+            for (int k = 0; k < d.n_bins; ++k) disp[k] += x;
+            block[d.off_dispx + b] = 0.0;
+        }
+    }
 }
 
 dmc_status run_opts_check(const dmc_run_opts &o)
@@ -334,7 +353,9 @@ int kernel_spec(const JobDev *jobs, int n_jobs)
     bool slab = true, half = true, grad = true;
     for (int i = 0; i < n_jobs; ++i) {
         const JobDev &d = jobs[i];
-        if (d.geom != GEOM_SLAB || d.src != SRC_WALLS || d.n_times > 0) slab = false;
+        if (d.geom != GEOM_SLAB || d.src != SRC_WALLS || d.n_times > 0 || d.wall_type[0] == WALL_PERIODIC ||
+            d.wall_type[1] == WALL_PERIODIC)
+            slab = false;
         if (d.geom != GEOM_HALF || d.src != SRC_GAUSSIAN || d.n_times == 0 || d.n_bins > 0 || d.off_kappa >= 0 ||
             d.n_hj > 0)
             half = false;
@@ -387,7 +408,10 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
         return fail(DMC_E_INVALID, "time-bounded launches need the persistent form");
     if (b.n_resume && !b.drain_iters) return fail(DMC_E_INVALID, "resuming needs a time-bounded launch");
     const size_t stats_lds = a.lds_stats ? (size_t)n_jobs * kStats * 8 : 0;
-    for (auto &d : devs) d.lds_bins = d.lds_kappa = d.lds_hj = -1;
+    for (auto &d : devs) {
+        d.lds_bins = d.lds_kappa = d.lds_hj = d.lds_dispx = -1;
+        d.disp_tel = (o.form == DMC_FORM_PERSISTENT && spec == GEOM_SLAB && !(b.drain_iters || b.n_resume)) ? 1 : 0;
+    }
     int block = 256, grid = 1;
     size_t lds_bytes = 0;
     if (o.form == DMC_FORM_PERSISTENT) {
@@ -405,6 +429,10 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
                     if ((size_t)(lo + n) <= budget) {
                         d.lds_bins = lo;
                         lo += n;
+                    }
+                    if ((size_t)(lo + d.n_batches) <= budget) {
+                        d.lds_dispx = lo;
+                        lo += d.n_batches;
                     }
                 }
                 if (d.off_kappa >= 0 && (size_t)(lo + 2) <= budget) {
@@ -557,6 +585,7 @@ dmc_status gather_jobs(const dmc_job *jobs, int32_t n_jobs, std::vector<JobHost>
         if (d.off_hj >= 0) d.off_hj += toff;
         if (d.off_snap >= 0) d.off_snap += toff;
         if (d.off_snap_abs >= 0) d.off_snap_abs += toff;
+        if (d.off_dispx >= 0) d.off_dispx += toff;
         toff += jh[i].size;
         d.times_off = (int32_t)tim;
         tim += (int64_t)jh[i].times.size();
@@ -820,7 +849,7 @@ extern "C" dmc_status dmc_simulate(const dmc_material *material, const dmc_geome
 extern "C" dmc_status dmc_tally_raw_size(const dmc_result *res, int32_t job, size_t *n)
 {
     if (!res || !n || job < 0 || job >= (int32_t)res->jobs.size()) return fail(DMC_E_INVALID, "bad result / job");
-    *n = (size_t)res->jobs[job].size;
+    *n = (size_t)(res->jobs[job].size - res->jobs[job].hidden);
     return DMC_OK;
 }
 
@@ -920,12 +949,13 @@ extern "C" dmc_status dmc_tally_read(const dmc_result *cres, int32_t job, int32_
         return DMC_OK;
     }
     if (q == DMC_Q_RAW) {
-        if (n < (size_t)h.size) return fail(DMC_E_INVALID, "output too small");
+        const size_t visible = (size_t)(h.size - h.hidden);
+        if (n < visible) return fail(DMC_E_INVALID, "output too small");
         const int64_t first = (d.off_bins >= 0)    ? d.off_bins
                               : (d.off_kappa >= 0) ? d.off_kappa
                               : (d.off_snap >= 0)  ? d.off_snap
                                                    : -1;
-        if (first >= 0) std::memcpy(mean, T + first, (size_t)h.size * sizeof(double));
+        if (first >= 0) std::memcpy(mean, T + first, visible * sizeof(double));
         return DMC_OK;
     }
     return fail(DMC_E_INVALID, "unknown quantity");

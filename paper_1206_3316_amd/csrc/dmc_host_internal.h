@@ -39,6 +39,7 @@ struct JobHost {
     double power = 0.0;       // steady: source power per unit area (slab, film) or length (cell); transient: energy
     double avg_volume = 1.0;  // mu(R) of the conductivity average
     int64_t size = 0;         // doubles of its tally block
+    int64_t hidden = 0;       // trailing doubles of the block that a caller does not read
     JobDev dev{};
 };
 

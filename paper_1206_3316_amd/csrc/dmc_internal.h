@@ -52,6 +52,9 @@ struct alignas(16) JobDev {
     int32_t stat_slot;      // index of this job's counters (the caller's job index)
     int32_t snap_abs_on;    // 0: every particle has the same sign, the host derives sum|s| = |sum s|
     uint64_t out_off;       // per-particle outputs of pid are at out_off + pid - pid0 (caller's job order)
+    int64_t off_dispx;      // bins: per-batch net transmissions (s per particle), expanded by the host
+    int32_t lds_dispx;      // -1: in global memory
+    int32_t disp_tel;       // 1: the displacement is telescoped (persistent slab kernel)
 };
 
 // A particle suspended at the end of a time-bounded launch (serving epochs):

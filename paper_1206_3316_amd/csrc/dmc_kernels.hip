@@ -268,7 +268,7 @@ __device__ __forceinline__ void set_kbin(Lane<R> &p)
     if (p.n_bins > 0) p.kbin = bin_of((p.geom != GEOM_FILM) ? p.z : p.x, p.bpl, p.n_bins);
 }
 
-template <typename R, int FORM>
+template <typename R, int FORM, int G>
 __device__ __forceinline__ void bin_enter(Lane<R> &p, const KArgs &a, const Shared &sh, int32_t k);
 
 // ------------------------------------------------------------ emission ----
@@ -381,6 +381,7 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
             p.x = c;
         p.last = wall;
         p.s = (R)J.wall_sign[wall];
+        if (J.disp_tel && wall == 1 && axis == 2) tadd(a, sh, J.lds_dispx, J.off_dispx, p.batch, -(double)p.s);
     } else if (src == SRC_GAUSSIAN) {
         const uint4 B = philox(plo, phi, 0u, TAG_EMIT_B, p.key0, p.key1);
         m = alias_draw(a.init_packed, a.init_bits, A.y);
@@ -442,32 +443,44 @@ __device__ __forceinline__ void bins_add(const Lane<R> &p, const KArgs &a, const
         tadd(a, sh, p.bl, p.bg, idx, v);
 }
 
+// Telescoped displacement (persistent slab kernel): the signed length a particle
+// adds to bin k over its whole path is s (F_k(z_end) - F_k(z_start)) with
+// F_k(z) = clamp(z - k w, 0, w), because the per-segment overlaps telescope along
+// a continuous path.  Slab particles start and end on a wall, where F_k is 0 (z =
+// 0) or w (z = L) for every bin, so a per-batch count of net transmissions
+// replaces the per-flight displacement sum; the host expands it into the bins.
+template <int FORM, int G>
+__device__ constexpr bool telescoped()
+{
+    return FORM == FORM_PERSISTENT && G == GEOM_SLAB;
+}
+
 // Per-lane bin cache (persistent form): entry A holds the sums of the bin the
 // particle is in, entry B those of the bin it came from, so a particle that
 // walks back and forth across one bin edge adds to registers only; an entry is
 // added to the tallies when a third bin displaces it or the particle ends.
-template <typename R, int FORM>
+template <typename R, int FORM, int G>
 __device__ __forceinline__ void flush_entry(Lane<R> &p, const KArgs &a, const Shared &sh, int32_t bin, double &s0,
                                             double &s1, double &s2)
 {
     if (bin < 0) return;
     bins_add<R, FORM>(p, a, sh, bin, s0);
     bins_add<R, FORM>(p, a, sh, bin + p.n_bins, s1);
-    bins_add<R, FORM>(p, a, sh, bin + 2 * p.n_bins, s2);
+    if (!telescoped<FORM, G>()) bins_add<R, FORM>(p, a, sh, bin + 2 * p.n_bins, s2);
     s0 = s1 = s2 = 0.0;
 }
 
-template <typename R, int FORM>
+template <typename R, int FORM, int G>
 __device__ __forceinline__ void bin_flush(Lane<R> &p, const KArgs &a, const Shared &sh)
 {
     if (FORM != FORM_PERSISTENT) return;  // the plain form adds every contribution directly
-    flush_entry<R, FORM>(p, a, sh, p.cbin, p.c0, p.c1, p.c2);
-    flush_entry<R, FORM>(p, a, sh, p.dbin, p.d0, p.d1, p.d2);
+    flush_entry<R, FORM, G>(p, a, sh, p.cbin, p.c0, p.c1, p.c2);
+    flush_entry<R, FORM, G>(p, a, sh, p.dbin, p.d0, p.d1, p.d2);
     p.cbin = p.dbin = -1;
 }
 
 // Makes entry A the one of bin k (the particle's new bin).
-template <typename R, int FORM>
+template <typename R, int FORM, int G>
 __device__ __forceinline__ void bin_enter(Lane<R> &p, const KArgs &a, const Shared &sh, int32_t k)
 {
     if (k == p.cbin) return;
@@ -482,27 +495,28 @@ __device__ __forceinline__ void bin_enter(Lane<R> &p, const KArgs &a, const Shar
     p.d1 = t1;
     p.d2 = t2;
     if (p.cbin != k) {
-        flush_entry<R, FORM>(p, a, sh, p.cbin, p.c0, p.c1, p.c2);
+        flush_entry<R, FORM, G>(p, a, sh, p.cbin, p.c0, p.c1, p.c2);
         p.cbin = k;
     }
 }
 
 // Time t spent in bin k: TIME += s t, PTIME += s t / tau, DISP += s v Omega_z t.
 // cached: k is the bin of entry A (persistent form); otherwise a direct add.
-template <typename R, int FORM>
+template <typename R, int FORM, int G>
 __device__ __forceinline__ void bin_add(Lane<R> &p, const KArgs &a, const Shared &sh, int k, R t, R vz, bool cached)
 {
+    constexpr bool T = telescoped<FORM, G>();
     const double d0 = (double)(p.s * t);
     const double d1 = (double)(p.s * Pr<R>::ptime(t, p.tau, p.itau));
-    const double d2 = (double)(p.s * vz * t);
+    const double d2 = T ? 0.0 : (double)(p.s * vz * t);
     if (FORM == FORM_PERSISTENT && cached) {
         p.c0 += d0;
         p.c1 += d1;
-        p.c2 += d2;
+        if (!T) p.c2 += d2;
     } else {
         bins_add<R, FORM>(p, a, sh, k, d0);
         bins_add<R, FORM>(p, a, sh, k + p.n_bins, d1);
-        bins_add<R, FORM>(p, a, sh, k + 2 * p.n_bins, d2);
+        if (!T) bins_add<R, FORM>(p, a, sh, k + 2 * p.n_bins, d2);
     }
 }
 
@@ -511,7 +525,7 @@ __device__ __forceinline__ void bin_add(Lane<R> &p, const KArgs &a, const Shared
 // current bin (every lane does the same work); a segment that leaves the bin
 // then moves the part beyond the bin's edge to the bins it reaches.  The plain
 // form adds each bin's part directly.
-template <typename R, int FORM>
+template <typename R, int FORM, int G>
 __device__ void score_bins(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, R seg)
 {
     const bool zax = (p.geom != GEOM_FILM);
@@ -521,7 +535,7 @@ __device__ void score_bins(Lane<R> &p, const KArgs &a, const Shared &sh, const J
     const int nb = p.n_bins;
     const int ka = p.kbin;  // bin_of(ca): the end bin of the previous segment
     if constexpr (FORM == FORM_PERSISTENT) {
-        bin_add<R, FORM>(p, a, sh, ka, seg, vz, true);
+        bin_add<R, FORM, G>(p, a, sh, ka, seg, vz, true);
         if (wa == (R)0) return;
         // the position update of the step computes exactly cb, so kb is the next
         // segment's start bin (a boundary interaction recomputes it)
@@ -537,29 +551,30 @@ __device__ void score_bins(Lane<R> &p, const KArgs &a, const Shared &sh, const J
         if (nin > 0) {
             const R tin = bw * inv;
             const int step = up ? 1 : -1;
-            for (int k = ka + step; k != kb; k += step) bin_add<R, FORM>(p, a, sh, k, tin, vz, false);
-            bin_add<R, FORM>(p, a, sh, ka, -((R)nin * tin), vz, true);
+            for (int k = ka + step; k != kb; k += step) bin_add<R, FORM, G>(p, a, sh, k, tin, vz, false);
+            bin_add<R, FORM, G>(p, a, sh, ka, -((R)nin * tin), vz, true);
         }
+        constexpr bool T = telescoped<FORM, G>();
         const double e0 = (double)(p.s * t1);
         const double e1 = (double)(p.s * Pr<R>::ptime(t1, p.tau, p.itau));
-        const double e2 = (double)(p.s * vz * t1);
+        const double e2 = T ? 0.0 : (double)(p.s * vz * t1);
         p.c0 -= e0;
         p.c1 -= e1;
-        p.c2 -= e2;
-        bin_enter<R, FORM>(p, a, sh, kb);
+        if (!T) p.c2 -= e2;
+        bin_enter<R, FORM, G>(p, a, sh, kb);
         p.c0 += e0;
         p.c1 += e1;
-        p.c2 += e2;
+        if (!T) p.c2 += e2;
     } else {
         if (wa == (R)0) {
-            bin_add<R, FORM>(p, a, sh, ka, seg, vz, false);
+            bin_add<R, FORM, G>(p, a, sh, ka, seg, vz, false);
             return;
         }
         const R cb = ca + wa * seg;
         const int kb = bin_of(cb, p.bpl, nb);
         p.kbin = kb;
         if (ka == kb) {
-            bin_add<R, FORM>(p, a, sh, ka, seg, vz, false);
+            bin_add<R, FORM, G>(p, a, sh, ka, seg, vz, false);
             return;
         }
         const R inv = Pr<R>::div((R)1, fabs(wa));
@@ -567,11 +582,11 @@ __device__ void score_bins(Lane<R> &p, const KArgs &a, const Shared &sh, const J
         const bool up = wa > (R)0;
         const R t0 = up ? fmax(((R)(ka + 1) * bw - ca) * inv, (R)0) : fmax((ca - (R)ka * bw) * inv, (R)0);
         const R t1 = up ? fmax((cb - (R)kb * bw) * inv, (R)0) : fmax(((R)(kb + 1) * bw - cb) * inv, (R)0);
-        bin_add<R, FORM>(p, a, sh, ka, t0, vz, false);
+        bin_add<R, FORM, G>(p, a, sh, ka, t0, vz, false);
         const R tin = bw * inv;
         const int step = up ? 1 : -1;
-        for (int k = ka + step; k != kb; k += step) bin_add<R, FORM>(p, a, sh, k, tin, vz, false);
-        bin_add<R, FORM>(p, a, sh, kb, t1, vz, false);
+        for (int k = ka + step; k != kb; k += step) bin_add<R, FORM, G>(p, a, sh, k, tin, vz, false);
+        bin_add<R, FORM, G>(p, a, sh, kb, t1, vz, false);
     }
 }
 
@@ -738,10 +753,10 @@ __device__ bool interact(Lane<R> &p, const JobDev &J, int32_t surf, const uint4 
 
 // ------------------------------------------------------- suspend / resume ----
 
-template <typename R, int FORM>
+template <typename R, int FORM, int G>
 __device__ void suspend(Lane<R> &p, const KArgs &a, const Shared &sh)
 {
-    if (p.n_bins > 0) bin_flush<R, FORM>(p, a, sh);
+    if (p.n_bins > 0) bin_flush<R, FORM, G>(p, a, sh);
     const uint32_t slot = atomicAdd(reinterpret_cast<unsigned int *>(a.queue + 1), 1u);
     Suspended &S = a.suspend_out[slot];  // the host sizes the buffer for every lane of the grid
     S.x = (double)p.x;
@@ -798,10 +813,21 @@ __device__ void resume(Lane<R> &p, const KArgs &a, const Shared &sh, uint32_t i)
 
 // ---------------------------------------------------------------- finish ----
 
-template <typename R, int FORM>
+template <typename R, int FORM, int G>
 __device__ void finish(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, bool capped)
 {
-    if (p.n_bins > 0) bin_flush<R, FORM>(p, a, sh);
+    if (p.n_bins > 0) bin_flush<R, FORM, G>(p, a, sh);
+    if (telescoped<FORM, G>() && p.n_bins > 0) {
+        // end term of the telescoped displacement: F_k(z_end) for every bin
+        const R z = p.z;
+        if (z >= p.len) {
+            tadd(a, sh, J.lds_dispx, J.off_dispx, p.batch, (double)p.s);
+        } else if (z > (R)0) {  // ended inside the slab (flight cap or truncation)
+            const int kz = bin_of(z, p.bpl, p.n_bins);
+            for (int kk = 0; kk < kz; ++kk) bins_add<R, FORM>(p, a, sh, kk + 2 * p.n_bins, (double)(p.s * p.bw));
+            bins_add<R, FORM>(p, a, sh, kz + 2 * p.n_bins, (double)(p.s * (z - (R)kz * p.bw)));
+        }
+    }
     if (J.off_kappa >= 0) {
         tadd(a, sh, J.lds_kappa, J.off_kappa, 0, p.Lz);
         tadd(a, sh, J.lds_kappa, J.off_kappa, 1, p.Lz * p.Lz);
@@ -852,7 +878,7 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
     const bool boundary = (tb <= dt);
     const R seg = boundary ? tb : dt;
     // step V: sample the segment
-    if (p.n_bins > 0) score_bins<R, FORM>(p, a, sh, J, seg);
+    if (p.n_bins > 0) score_bins<R, FORM, G>(p, a, sh, J, seg);
     const bool gradient = (G == GEOM_GRAD) || ((G == GEOM_ANY) && (p.src == SRC_GRADIENT));
     if (gradient) {
         const double dz = (double)(p.s * p.v * p.oz * seg);
@@ -885,7 +911,7 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
         if (interact(p, J, surf, w)) return 1;
         if (p.n_bins > 0) {
             set_kbin(p);  // a periodic face moves the particle to the other end
-            if (FORM == FORM_PERSISTENT) bin_enter<R, FORM>(p, a, sh, p.kbin);
+            if (FORM == FORM_PERSISTENT) bin_enter<R, FORM, G>(p, a, sh, p.kbin);
         }
     } else {                                                          // step IVb
         const uint32_t m = alias_draw(sh.gain, a.gain_bits, w.y);
@@ -968,6 +994,12 @@ __device__ void flush_shared(const KArgs &a, const Shared &sh)
                     if (v != 0.0) gadd(a.tally + J.off_bins + i, v);
                 }
             }
+            if (J.lds_dispx >= 0) {
+                for (int i = threadIdx.x; i < J.n_batches; i += blockDim.x) {
+                    const double v = sh.ltally[J.lds_dispx + i];
+                    if (v != 0.0) gadd(a.tally + J.off_dispx + i, v);
+                }
+            }
             if (J.lds_kappa >= 0 && threadIdx.x < 2) {
                 const double v = sh.ltally[J.lds_kappa + threadIdx.x];
                 if (v != 0.0) gadd(a.tally + J.off_kappa + threadIdx.x, v);
@@ -1005,7 +1037,7 @@ __global__ void __launch_bounds__(256) plain_kernel(KArgs a)
         do {
             r = step<R, FORM_PLAIN, G>(p, a, sh, J);
         } while (r == 0);
-        finish<R, FORM_PLAIN>(p, a, sh, J, r == 2);
+        finish<R, FORM_PLAIN, G>(p, a, sh, J, r == 2);
     }
     flush_shared(a, sh);
 }
@@ -1084,7 +1116,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
             // this wave hands its live particles, and any indices of its chunk not yet
             // started, to the next launch
             if (++drain > a.drain_iters) {
-                if (alive) suspend<R, FORM_PERSISTENT>(p, a, sh);
+                if (alive) suspend<R, FORM_PERSISTENT, G>(p, a, sh);
                 alive = false;
                 while (pool_cur < pool_end) {
                     const uint64_t avail = pool_end - pool_cur;
@@ -1097,7 +1129,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                             job = find_job(a, q - (uint64_t)a.n_resume, job);
                             emit<R, G>(p, a, sh, a.jobs[job], q, job);
                         }
-                        suspend<R, FORM_PERSISTENT>(p, a, sh);
+                        suspend<R, FORM_PERSISTENT, G>(p, a, sh);
                     }
                     pool_cur += (avail < 64u) ? avail : 64u;
                 }
@@ -1124,7 +1156,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
             const JobDev &J = a.jobs[p.job];
             const int r = step<R, FORM_PERSISTENT, G>(p, a, sh, J);
             if (r != 0) {
-                finish<R, FORM_PERSISTENT>(p, a, sh, J, r == 2);
+                finish<R, FORM_PERSISTENT, G>(p, a, sh, J, r == 2);
                 alive = false;
             }
         }
