@@ -111,12 +111,15 @@ def launch_params(jobs, mat, precision="fp32", stream=None, overrides=None, tune
 
 def other_workloads(b, di, mat, mat_in, stream):
     """One autotuned launch each of the transient heated spot (1e9 particles,
-    64^3 grid x 50 times) and of the 64 batched nanostructures (1e6-1e8
-    particles each, K_max = 40), after the tuner's trials have loaded the
+    64^3 grid x 50 times), of the 64 batched nanostructures (1e6-1e8 particles
+    each, K_max = 40), and of the same batch with first-event termination for
+    its 24 films (exact for films), after the tuner's trials have loaded the
     kernels.  Reported beside the headline, not in it."""
     res = {}
     for name, jobs in (("heated_spot_1e9_64cube_50times", [di.heated_spot(material=mat_in)]),
-                       ("nanostructures_64_instances", di.batched_nanostructures(material=mat_in))):
+                       ("nanostructures_64_instances", di.batched_nanostructures(material=mat_in)),
+                       ("nanostructures_64_instances_first_event_films",
+                        di.batched_nanostructures(material=mat_in, first_event_films=True))):
         t0 = time.perf_counter()
         params = launch_params(jobs, mat, stream=stream)
         tune_s = time.perf_counter() - t0

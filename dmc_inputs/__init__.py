@@ -169,6 +169,7 @@ class Tally:
     grid: Tuple[int, int, int] = (0, 0, 0)  # snapshot grid cells along x, y, z
     grid_lo: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     grid_hi: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    first_event: bool = False  # in-plane films: end at the first scattering event or diffuse reflection
 
 
 @dataclass
@@ -235,12 +236,14 @@ def heated_spot(n: int = 1_000_000_000, seed: int = 7, material: Optional[Materi
 
 
 def in_plane_film(d: float, specularity: float, n: int, seed: int, material: Optional[Material] = None,
-                  gradient: float = -1e6, kmax: int = 40, n_hj: int = 40, n_bins: int = 0) -> Job:
+                  gradient: float = -1e6, kmax: int = 40, n_hj: int = 40, n_bins: int = 0,
+                  first_event: bool = False) -> Job:
     mat = material or silicon_like()
     w = Wall("adiabatic", specularity=specularity)
     geom = Geometry("film_x", length=d, walls=[w, Wall("adiabatic", specularity=specularity)])
-    return Job(mat, geom, Source("gradient", gradient=gradient), Tally(n_bins=n_bins, kmax=kmax, n_hj=n_hj),
-               int(n), int(seed), f"film_d{d:.3g}_p{specularity}")
+    tally = Tally(n_bins=n_bins, kmax=kmax, n_hj=n_hj, first_event=first_event)
+    return Job(mat, geom, Source("gradient", gradient=gradient), tally, int(n), int(seed),
+               f"film_d{d:.3g}_p{specularity}" + ("_first" if first_event else ""))
 
 
 def pore_cell(period: float, porosity: float, n: int, seed: int, material: Optional[Material] = None,
@@ -254,7 +257,7 @@ def pore_cell(period: float, porosity: float, n: int, seed: int, material: Optio
 
 
 def batched_nanostructures(n_scale: float = 1.0, seed: int = 4, material: Optional[Material] = None,
-                           n_min: float = 1e6, n_max: float = 1e8) -> List[Job]:
+                           n_min: float = 1e6, n_max: float = 1e8, first_event_films: bool = False) -> List[Job]:
     """64 instances: 24 in-plane films (8 thicknesses 20-500 nm x p in {0, .5, .9}) and
     40 pore cells (porosity {.1,.2,.3,.4} x 10 periods 50-500 nm).  Particle counts are
     log-uniform in [n_min, n_max] (numpy PCG64 with ``seed``), times ``n_scale``."""
@@ -265,7 +268,8 @@ def batched_nanostructures(n_scale: float = 1.0, seed: int = 4, material: Option
     i = 0
     for d in 20e-9 * (500 / 20) ** (np.arange(8) / 7):
         for p in (0.0, 0.5, 0.9):
-            jobs.append(in_plane_film(float(d), p, max(1, int(counts[i] * n_scale)), 1000 + i, mat))
+            jobs.append(in_plane_film(float(d), p, max(1, int(counts[i] * n_scale)), 1000 + i, mat,
+                                      first_event=first_event_films))
             i += 1
     for phi in (0.1, 0.2, 0.3, 0.4):
         for P in 50e-9 * (500 / 50) ** (np.arange(10) / 9):

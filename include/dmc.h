@@ -141,6 +141,14 @@ typedef struct {
     int32_t grid[3];   /* transient snapshot grid cells along x, y, z */
     double grid_lo[3]; /* snapshot grid bounds [m] */
     double grid_hi[3];
+    int32_t first_event; /* in-plane films (DMC_GEOM_FILM_X, gradient source) only: 1 ends every
+                            trajectory at its first scattering event or first diffuse wall
+                            reflection.  Exact for films (the thin-film special case of the
+                            periodic-nanostructure application): afterwards the direction is
+                            isotropic or Lambertian about the wall normal and the film is
+                            invariant along z, so the flux still to come averages to zero.
+                            Specular reflections continue the free path.  Rejected elsewhere. */
+    int32_t pad0;
 } dmc_tally_desc;
 
 /* ------------------------------------------------------------------------ */

@@ -68,6 +68,7 @@ class Problem(C.Structure):
         ("n_times", C.c_int32), ("times", C.POINTER(C.c_double)),
         ("grid", C.c_int32 * 3), ("grid_lo", C.c_double * 3), ("grid_hi", C.c_double * 3),
         ("seed", C.c_uint64),
+        ("first_event", C.c_int32),
     ]
 
 
@@ -273,6 +274,9 @@ def prepare(job: di.Job) -> Prepared:
         power = C_tot * abs(src.dT) * math.pi ** 1.5 * src.radius ** 3 / 2.0
         P.n_src = 1
     P.n_bins, P.n_batches, P.kmax, P.n_hj = int(tl.n_bins), int(tl.n_batches), int(tl.kmax), int(tl.n_hj)
+    P.first_event = int(bool(getattr(tl, "first_event", False)))
+    if P.first_event and (job.geometry.kind != "film_x" or job.source.kind != "gradient"):
+        raise ValueError("first-event termination applies to in-plane films under the gradient source")
     if tl.kmax >= 0 and tl.n_hj > tl.kmax:
         raise ValueError("n_hj must not exceed kmax")
     times = np.ascontiguousarray(tl.times, dtype=np.float64)

@@ -306,6 +306,9 @@ typedef struct {
     const double *times;
     int32_t grid[3]; double grid_lo[3], grid_hi[3];
     uint64_t seed;
+    /* in-plane film: end a trajectory at its first scattering event or first
+     * diffuse wall reflection (the flux carried afterwards averages to zero) */
+    int32_t first_event;
 } oracle_problem;
 
 typedef struct {
@@ -513,8 +516,12 @@ static int wall_interaction(const oracle_problem *P, particle *p, int32_t surf, 
         return 0;
     }
     /* adiabatic: specular with probability p, else diffuse (Lambertian about the inward normal) */
-    if ((uint64_t)w[1] < P->wall_spec[wall]) p->o[ax] = -p->o[ax];
-    else lambertian_plane(ax, (wall == 0) ? 1.0 : -1.0, w[2], w[3], p->o);
+    if ((uint64_t)w[1] < P->wall_spec[wall]) {
+        p->o[ax] = -p->o[ax];
+    } else {
+        if (P->first_event) return 1; /* a diffuse reflection ends the first free path */
+        lambertian_plane(ax, (wall == 0) ? 1.0 : -1.0, w[2], w[3], p->o);
+    }
     p->last = wall;
     return 0;
 }
@@ -642,6 +649,7 @@ int oracle_run(const oracle_problem *P, uint64_t pid0, uint64_t pid1, double *ta
                 ++nscat;
                 cnt->scatters++;
                 if (P->kmax >= 0 && nscat >= (uint32_t)P->kmax) { t = t_new; break; }
+                if (P->first_event) { t = t_new; break; }              /* the first free path ends here */
             }
             t = t_new;
             if (k >= OR_ITER_CAP) { cnt->capped++; break; }

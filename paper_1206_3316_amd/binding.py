@@ -49,7 +49,8 @@ class dmc_source(C.Structure):
 
 class dmc_tally_desc(C.Structure):
     _fields_ = [("n_bins", C.c_int32), ("n_batches", C.c_int32), ("kmax", C.c_int32), ("n_hj", C.c_int32),
-                ("grid", C.c_int32 * 3), ("grid_lo", C.c_double * 3), ("grid_hi", C.c_double * 3)]
+                ("grid", C.c_int32 * 3), ("grid_lo", C.c_double * 3), ("grid_hi", C.c_double * 3),
+                ("first_event", C.c_int32), ("pad0", C.c_int32)]
 
 
 class dmc_run_opts(C.Structure):
@@ -340,6 +341,7 @@ def job_struct(job, material: Material, keep: list) -> dmc_job:
     t = job.tally
     td = dmc_tally_desc()
     td.n_bins, td.n_batches, td.kmax, td.n_hj = int(t.n_bins), int(t.n_batches), int(t.kmax), int(t.n_hj)
+    td.first_event = int(bool(getattr(t, "first_event", False)))
     for i in range(3):
         td.grid[i] = int(t.grid[i])
         td.grid_lo[i] = float(t.grid_lo[i])

@@ -167,6 +167,8 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
     if (t.kmax < -1) return fail(DMC_E_INVALID, "kmax must be >= -1");
     if (t.n_hj < 0 || t.n_hj > kMaxHj || (t.n_hj > 0 && (t.kmax < 0 || t.n_hj > t.kmax)))
         return fail(DMC_E_INVALID, "n_hj must be in 0..kmax");
+    if (t.first_event != 0 && (t.first_event != 1 || g.kind != DMC_GEOM_FILM_X || s.kind != DMC_SRC_GRADIENT))
+        return fail(DMC_E_INVALID, "first_event applies to in-plane films under the gradient source");
     if (jb.n_times < 0 || jb.n_times > kMaxTimes || (jb.n_times > 0 && !jb.times))
         return fail(DMC_E_INVALID, "bad snapshot times");
     h.job = jb;
@@ -193,7 +195,8 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
     }
     d.n_bins = t.n_bins;
     d.n_batches = t.n_batches;
-    d.kmax = t.kmax;
+    d.kmax = t.first_event ? 1 : t.kmax;  // first-event termination: one scattering event at most
+    d.first_event = t.first_event;
     d.n_hj = t.n_hj;
     d.n_times = jb.n_times;
     d.lds_bins = d.lds_kappa = d.lds_hj = -1;

@@ -55,6 +55,8 @@ struct alignas(16) JobDev {
     int64_t off_dispx;      // bins: per-batch net transmissions (s per particle), expanded by the host
     int32_t lds_dispx;      // -1: in global memory
     int32_t disp_tel;       // 1: the displacement is telescoped (persistent slab kernel)
+    int32_t first_event;    // 1: a diffuse wall reflection (or the first scattering event) ends the particle
+    int32_t pad2;
 };
 
 // A particle suspended at the end of a time-bounded launch (serving epochs):

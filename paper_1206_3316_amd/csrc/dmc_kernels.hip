@@ -745,6 +745,7 @@ __device__ bool interact(Lane<R> &p, const JobDev &J, int32_t surf, const uint4 
         else
             p.ox = -p.ox;
     } else {
+        if (J.first_event) return true;  // a diffuse reflection ends the first free path
         lambertian_plane(p, ax, wall == 0 ? (R)1 : (R)-1, w.z, w.w);
     }
     p.last = wall;

@@ -40,6 +40,8 @@ def parity_cases():
         "mixed_slab": mixed_slab(),
         "film_p0.5": di.in_plane_film(60e-9, 0.5, 20_000, seed=103, material=si, kmax=40, n_hj=40, n_bins=8),
         "film_gray_p0": di.in_plane_film(100e-9, 0.0, 20_000, seed=104, material=gray, kmax=10, n_hj=10),
+        "film_first_event": di.in_plane_film(60e-9, 0.5, 40_000, seed=107, material=si, kmax=40, n_hj=4,
+                                             first_event=True),
         "pore_cell": di.pore_cell(100e-9, 0.3, 20_000, seed=105, material=si, kmax=40, n_hj=40),
         "pore_cell_specular": di.pore_cell(80e-9, 0.2, 10_000, seed=106, material=gray, kmax=20, n_hj=5,
                                            specularity=0.7),

@@ -202,6 +202,30 @@ def test_batched_nanostructures_full_size(si):
     assert float(np.sum(z ** 2)) <= 73.4, z  # chi-square, 40 degrees of freedom, 99.9 %
 
 
+def test_nanostructure_films_first_event_full_size(si):
+    """The 24 films of the batch with first-event termination: same
+    Fuchs-Sondheimer conductivities, a fraction of the flights."""
+    mat, lm = si
+    films = [j for j in di.batched_nanostructures(material=mat, first_event_films=True)
+             if j.geometry.kind == "film_x"]
+    full = [j for j in di.batched_nanostructures(material=mat) if j.geometry.kind == "film_x"]
+    assert len(films) == 24
+    res = b.simulate(films, material=lm, **bench.launch_params(films, lm))
+    ref_run = b.simulate(full, material=lm, **bench.launch_params(full, lm))
+    fl_first = sum(res.stats(i).iterations for i in range(24))
+    fl_full = sum(ref_run.stats(i).iterations for i in range(24))
+    print(f"films: first-event {fl_first:.3e} flights in {res.stats(0).kernel_ms:.1f} ms, "
+          f"K_max = 40 {fl_full:.3e} flights in {ref_run.stats(0).kernel_ms:.1f} ms", flush=True)
+    assert fl_first < 0.5 * fl_full
+    for i, job in enumerate(films):
+        st = res.stats(i)
+        assert st.particles == job.n_particles and st.capped == 0 and st.scatters <= job.n_particles
+        k, kse = res.read(i, b.Q_KAPPA)
+        ref = _kappa_fs(mat, job.geometry.length, job.geometry.walls[0].specularity)
+        assert kse[0] < 1e-2 * ref, job.name
+        assert abs(k[0] - ref) <= max(4.0 * kse[0], 1e-3 * ref), (job.name, k[0], ref, kse[0])
+
+
 @pytest.mark.parametrize("i", [0, 23, 24, 63])
 def test_batched_nanostructure_fp64_slices_match_oracle(si, i):
     mat, lm = si

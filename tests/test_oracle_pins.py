@@ -340,6 +340,47 @@ def test_in_plane_film_fuchs_sondheimer_silicon():
     assert res["kappa_se"] < 0.03 * ref
 
 
+@pytest.mark.parametrize("p", [0.0, 0.5, 0.9])
+def test_first_event_termination_is_exact_for_films(p):
+    """In-plane films: ending each trajectory at its first scattering event or
+    first diffuse reflection keeps the Fuchs-Sondheimer conductivity (the flux
+    carried afterwards averages to zero), and costs a fraction of the flights."""
+    mat = di.gray_material()
+    Cm, vg, tau, kb = _kappa_bulk(mat)
+    lam = float(vg[0] * tau[0])
+    ref = kb * refsol.fuchs_sondheimer_S(1.0, p)
+    full = di.in_plane_film(lam, p, 100_000, seed=43, material=mat, kmax=10, n_hj=0)
+    first = di.in_plane_film(lam, p, 100_000, seed=43, material=mat, kmax=10, n_hj=0, first_event=True)
+    r1, _, c1, _ = oracle.simulate(first, threads=THREADS)
+    r0, _, c0, _ = oracle.simulate(full, threads=THREADS)
+    assert abs(r1["kappa"] - ref) <= 4 * r1["kappa_se"], (r1["kappa"], ref, r1["kappa_se"])
+    assert r1["kappa_se"] < 0.03 * ref
+    assert c1["scatters"] <= first.n_particles  # at most one scattering event each
+    assert c1["iterations"] < 0.5 * c0["iterations"]
+    # same particles, same first free paths: the truncated run differs from the
+    # full one only by terms of zero mean
+    assert abs(r1["kappa"] - r0["kappa"]) <= 4 * r0["kappa_se"]
+
+
+def test_first_event_termination_silicon_film():
+    mat = di.silicon_like()
+    Cm, vg, tau, kb = _kappa_bulk(mat)
+    d = 100e-9
+    job = di.in_plane_film(d, 0.5, 200_000, seed=44, material=mat, kmax=40, n_hj=0, first_event=True)
+    res, *_ = oracle.simulate(job, threads=THREADS)
+    S = refsol.fuchs_sondheimer_S(d / (vg * tau), 0.5, n=4000)
+    ref = float(np.sum(Cm * vg * vg * tau / 3.0 * S))
+    assert abs(res["kappa"] - ref) <= 4 * res["kappa_se"], (res["kappa"], ref, res["kappa_se"])
+    assert res["kappa_se"] < 0.03 * ref
+
+
+def test_first_event_rejected_outside_films():
+    job = di.pore_cell(100e-9, 0.2, 10, seed=1, material=di.gray_material(), kmax=4, n_hj=0)
+    job.tally.first_event = True
+    with pytest.raises(ValueError):
+        oracle.prepare(job)
+
+
 def test_film_flux_after_first_event_vanishes():
     """Diffuse walls and isotropic scattering: the mean contribution after the first
     scattering event is zero (H_j, j >= 1) and H_0 carries the whole conductivity."""
