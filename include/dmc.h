@@ -261,6 +261,47 @@ typedef struct {
 dmc_status dmc_autotune(const dmc_job *jobs, int32_t n_jobs, const dmc_run_opts *base, dmc_tune_opts *tune,
                         dmc_run_opts *best);
 
+/* ---- Truncation planning for periodic problems (gradient source) ----
+ * Trajectories under periodic boundaries never end, so they are cut after
+ * K_max scattering events.  The mean flux carried between scattering events j
+ * and j+1, <H_j>, decays with j (exponentially after a few events, in the
+ * paper's periodic-nanostructure application); cutting at K discards the sum
+ * of <H_j> over j >= K.  This call runs a pilot of n_pilot particles (ids
+ * first_particle + n_particles onwards of the job's seed, disjoint from the
+ * job's own) tracked for k_pilot events and finds the run j = 1..n of events
+ * whose |<H_j>| exceeds 4 pilot standard errors (n_fit = n); unless n_pilot is
+ * given, a pilot resolving fewer than 3 is grown tenfold up to min(N, 1e7).
+ * It returns:
+ *   k_uncertain: the first j >= 1 whose |<H_j>| is at most its standard error
+ *     at the job's n_particles (the paper's empirical criterion);
+ *   decay, amplitude: |<H_j>| ~ amplitude * decay^j for j >= 1: a log-linear fit
+ *     weighted by (|<H_j>| / se_j)^2 over j = 1..n when n >= 3, the ratio
+ *     |<H_2>| / |<H_1>| when n = 2, the upper bound 4 se_2 / |<H_1>| when n = 1;
+ *   kmax: the smallest K > n whose tail sum amplitude decay^K / (1 - decay) is
+ *     at most bias_fraction times the standard error of kappa at n_particles,
+ *     and bias_bound that tail sum [W/m/K]; when n = 0 (no flux after the first
+ *     event is resolved; exactly zero in expectation for films) kmax = 1; when
+ *     no decay below 1 is found, fit_ok = 0 and kmax = max(n + 1, k_uncertain);
+ *     in those two cases bias_bound is |the pilot's sum of <H_j> beyond kmax|;
+ *   kappa_se: the predicted standard error of kappa at n_particles.
+ * The job must have a gradient source.  Synchronous on opts->stream. */
+typedef struct {
+    uint64_t n_pilot;     /* 0: min(n_particles, 1e6), grown as above */
+    int32_t k_pilot;      /* 0: 200 (3 .. 1024) */
+    int32_t pad0;
+    double bias_fraction; /* 0: 0.2 */
+} dmc_trunc_opts;
+
+typedef struct {
+    int32_t kmax, k_uncertain, fit_ok, n_fit;
+    double decay, amplitude, bias_bound, kappa_se;
+    double kappa_pilot;   /* the pilot's kappa with k_pilot events [W/m/K] */
+    uint64_t n_pilot;     /* pilot particles used */
+} dmc_trunc_plan;
+
+dmc_status dmc_plan_truncation(const dmc_job *job, const dmc_run_opts *opts, const dmc_trunc_opts *t,
+                               dmc_trunc_plan *out);
+
 #define DMC_Q_T 0          /* energy temperature T - T_eq per bin [K] (n = n_bins) */
 #define DMC_Q_TLOC 1       /* pseudo-temperature T_loc - T_eq per bin [K] */
 #define DMC_Q_FLUX 2       /* heat flux along z per bin [W/m^2] */

@@ -82,6 +82,16 @@ class dmc_tune_opts(C.Structure):
                 ("from_cache", C.c_int32)]
 
 
+class dmc_trunc_opts(C.Structure):
+    _fields_ = [("n_pilot", C.c_uint64), ("k_pilot", C.c_int32), ("pad0", C.c_int32), ("bias_fraction", C.c_double)]
+
+
+class dmc_trunc_plan(C.Structure):
+    _fields_ = [("kmax", C.c_int32), ("k_uncertain", C.c_int32), ("fit_ok", C.c_int32), ("n_fit", C.c_int32),
+                ("decay", C.c_double), ("amplitude", C.c_double), ("bias_bound", C.c_double),
+                ("kappa_se", C.c_double), ("kappa_pilot", C.c_double), ("n_pilot", C.c_uint64)]
+
+
 class dmc_server_opts(C.Structure):
     _fields_ = [("memory_budget", C.c_size_t), ("max_active", C.c_int32), ("epoch_flights", C.c_uint64),
                 ("drain_flights", C.c_uint32), ("run", dmc_run_opts)]
@@ -105,6 +115,8 @@ _SIGS = {
                            C.c_int32),
     "dmc_autotune": ([C.POINTER(dmc_job), C.c_int32, C.POINTER(dmc_run_opts), C.POINTER(dmc_tune_opts),
                       C.POINTER(dmc_run_opts)], C.c_int32),
+    "dmc_plan_truncation": ([C.POINTER(dmc_job), C.POINTER(dmc_run_opts), C.POINTER(dmc_trunc_opts),
+                             C.POINTER(dmc_trunc_plan)], C.c_int32),
     "dmc_tally_read": ([C.c_void_p, C.c_int32, C.c_int32, C.c_int32, f64p, f64p, C.c_size_t], C.c_int32),
     "dmc_tally_raw_size": ([C.c_void_p, C.c_int32, C.POINTER(C.c_size_t)], C.c_int32),
     "dmc_result_stats": ([C.c_void_p, C.c_int32, C.POINTER(dmc_stats)], C.c_int32),
@@ -199,6 +211,10 @@ def dmc_simulate_batch(jobs, n_jobs, opts, out):
 
 def dmc_autotune(jobs, n_jobs, base, tune, best):
     return _call("dmc_autotune", jobs, n_jobs, base, tune, best)
+
+
+def dmc_plan_truncation(job, opts, t, out):
+    return _call("dmc_plan_truncation", job, opts, t, out)
 
 
 def dmc_tally_read(res, job, quantity, time_index, mean, se, n):
@@ -489,6 +505,20 @@ def autotune(jobs, material: Optional[Material] = None, precision="fp32", stream
     trials = [{"block": r.block, "chunk": r.chunk, "refill_min": r.refill_min, "lds_tally": r.lds_tally,
                "pilot": r.pilot, "ms": r.ms, "flights_per_s": r.flights_per_s} for r in buf[:min(t.n_trials, 64)]]
     return {k: int(getattr(best, k)) for k in TUNED_PARAMS}, trials
+
+
+def plan_truncation(job, material: Optional[Material] = None, precision="fp32", stream=None, n_pilot=0, k_pilot=0,
+                    bias_fraction=0.0) -> dict:
+    """Truncation K_max for a gradient-source job from a pilot run (see dmc_plan_truncation)."""
+    material = material or Material(job.material)
+    keep: list = [material]
+    j = job_struct(job, material, keep)
+    o = run_opts(precision, "persistent", getattr(stream, "cuda_stream", stream))
+    t = dmc_trunc_opts()
+    t.n_pilot, t.k_pilot, t.bias_fraction = int(n_pilot), int(k_pilot), float(bias_fraction)
+    out = dmc_trunc_plan()
+    dmc_plan_truncation(C.byref(j), C.byref(o), C.byref(t), C.byref(out))
+    return {f: getattr(out, f) for f, _ in dmc_trunc_plan._fields_}
 
 
 def workspace_bytes(jobs, material: Material, precision="fp32", form="persistent") -> int:

@@ -1,4 +1,5 @@
-// dmc_tune.cpp -- autotuner of the persistent form's launch parameters.
+// dmc_tune.cpp -- planning helpers: the autotuner of the persistent form's
+// launch parameters, and truncation planning for periodic problems.
 //
 // A batch's throughput depends on the block size (waves per CU against LDS
 // per workgroup), the queue chunk (queue atomics against lanes left idle at the
@@ -232,5 +233,150 @@ extern "C" dmc_status dmc_autotune(const dmc_job *jobs, int32_t n_jobs, const dm
         std::lock_guard<std::mutex> g(g_cache_mu);
         g_cache[key] = cur;
     }
+    return DMC_OK;
+}
+
+// ------------------------------------------------------ truncation planning ----
+
+namespace {
+
+// One pilot: H_j and its standard error (j < kp), kappa and its standard error.
+dmc_status run_pilot(const dmc_job &job, const dmc_run_opts &o, uint64_t n_pilot, int32_t kp, std::vector<double> &hj,
+                     std::vector<double> &hse, double &kap, double &kse)
+{
+    dmc_job pj = job;  // the next n_pilot particle ids of the same realisation
+    pj.first_particle = job.first_particle + job.n_particles;
+    pj.n_particles = n_pilot;
+    pj.tally.kmax = kp;
+    pj.tally.n_hj = kp;
+    pj.tally.first_event = 0;
+    std::vector<JobHost> jh;
+    dmc_status st = gather_jobs(&pj, 1, jh);
+    if (st != DMC_OK) return st;
+    dmc_result *r = nullptr;
+    if ((st = launch(jh, o, &r)) != DMC_OK) return st;
+    hj.assign(kp, 0.0);
+    hse.assign(kp, 0.0);
+    st = dmc_tally_read(r, 0, DMC_Q_HJ, 0, hj.data(), hse.data(), (size_t)kp);
+    if (st == DMC_OK) st = dmc_tally_read(r, 0, DMC_Q_KAPPA, 0, &kap, &kse, 1);
+    dmc_result_destroy(r);
+    return st;
+}
+
+}  // namespace
+
+extern "C" dmc_status dmc_plan_truncation(const dmc_job *job, const dmc_run_opts *opts, const dmc_trunc_opts *t,
+                                          dmc_trunc_plan *out)
+{
+    if (!job || !out) return fail(DMC_E_INVALID, "job / out is NULL");
+    *out = dmc_trunc_plan{};
+    if (job->source.kind != DMC_SRC_GRADIENT) return fail(DMC_E_INVALID, "truncation planning needs a gradient source");
+    dmc_run_opts o;
+    if (opts)
+        o = *opts;
+    else
+        dmc_run_opts_default(&o);
+    o.workspace = nullptr;
+    o.workspace_bytes = 0;
+    o.nscat_out = nullptr;
+    dmc_status st = run_opts_check(o);
+    if (st != DMC_OK) return st;
+    const uint64_t N = job->n_particles;
+    const bool fixed = t && t->n_pilot;
+    uint64_t n_pilot = fixed ? t->n_pilot : std::min<uint64_t>(N, 1000000);
+    const int32_t kp = (t && t->k_pilot) ? t->k_pilot : 200;
+    const double frac = (t && t->bias_fraction > 0.0) ? t->bias_fraction : 0.2;
+    if (n_pilot < 2 || kp < 3 || kp > kMaxHj) return fail(DMC_E_INVALID, "n_pilot >= 2 and 3 <= k_pilot <= 1024");
+    if (N < 1 || job->first_particle + N + (fixed ? n_pilot : std::max<uint64_t>(n_pilot, 10000000)) <
+                     job->first_particle)
+        return fail(DMC_E_INVALID, "particle ids overflow");
+
+    // The run of significant events j = 1, 2, ..., n: |<H_j>| above 4 pilot
+    // standard errors; the first insignificant event ends it, so chance
+    // excursions further out do not count.  A pilot that resolves fewer than 3
+    // is grown tenfold (to at most min(N, 1e7) particles) unless its size was given.
+    std::vector<double> hj, hse;
+    double kap = 0.0, kse = 0.0;
+    int n = 0;
+    for (;;) {
+        if ((st = run_pilot(*job, o, n_pilot, kp, hj, hse, kap, kse)) != DMC_OK) return st;
+        n = 0;
+        while (n + 1 < kp && std::fabs(hj[n + 1]) > 4.0 * hse[n + 1]) ++n;
+        const uint64_t cap = std::min<uint64_t>(N, 10000000);
+        if (fixed || n >= 3 || n_pilot >= cap) break;
+        n_pilot = std::min<uint64_t>(cap, n_pilot * 10);
+    }
+    out->n_fit = n;
+    out->n_pilot = n_pilot;
+
+    // standard errors of the job itself scale as 1/sqrt(N)
+    const double scale = std::sqrt((double)n_pilot / (double)N);
+    out->kappa_pilot = kap;
+    out->kappa_se = kse * scale;
+    out->k_uncertain = kp;
+    for (int j = 1; j < kp; ++j)
+        if (std::fabs(hj[j]) <= hse[j] * scale) {
+            out->k_uncertain = j;
+            break;
+        }
+    if (n == 0) {
+        // nothing after the first event is distinguishable from zero at the
+        // pilot's size (exactly zero in expectation for films): the pilot's
+        // signed sum beyond the first event is the estimate of what is cut
+        out->kmax = 1;
+        out->fit_ok = 1;
+        double tail = 0.0;
+        for (int j = 1; j < kp; ++j) tail += hj[j];
+        out->bias_bound = std::fabs(tail);
+        return DMC_OK;
+    }
+    // Exponential tail |<H_j>| ~ A r^j after the first free path (j = 0 is not
+    // part of the decay): n >= 3, a log-linear fit weighted by (|<H_j>| / se_j)^2,
+    // the inverse variance of ln|<H_j>|; n = 2, the ratio of the two events;
+    // n = 1, the upper bound 4 se_2 / |<H_1>| on the first step into the noise.
+    double rr = 0.0, A = 0.0;
+    if (n >= 3) {
+        double sw = 0, sx = 0, sy = 0, sxx = 0, sxy = 0;
+        for (int j = 1; j <= n; ++j) {
+            const double h = std::fabs(hj[j]);
+            const double w = (hse[j] > 0.0) ? (h / hse[j]) * (h / hse[j]) : 1.0;
+            const double y = std::log(h);
+            sw += w;
+            sx += w * j;
+            sy += w * y;
+            sxx += w * (double)j * j;
+            sxy += w * j * y;
+        }
+        const double den = sw * sxx - sx * sx;
+        if (den > 0.0) {
+            const double slope = (sw * sxy - sx * sy) / den;
+            rr = std::exp(slope);
+            A = std::exp((sy - slope * sx) / sw);
+        } else {
+            rr = 1.0;
+        }
+    } else {
+        rr = (n == 2) ? std::fabs(hj[2]) / std::fabs(hj[1]) : 4.0 * hse[2] / std::fabs(hj[1]);
+        A = std::fabs(hj[n]) / std::pow(rr, n);
+    }
+    if (!(rr < 1.0) || !(rr > 0.0)) {
+        // no decay resolved: the paper's empirical criterion, and the pilot's own
+        // signed sum beyond it as the estimate of what is cut
+        out->kmax = std::min(kp, std::max(n + 1, out->k_uncertain));
+        out->fit_ok = 0;
+        double tail = 0.0;
+        for (int j = out->kmax; j < kp; ++j) tail += hj[j];
+        out->bias_bound = std::fabs(tail);
+        return DMC_OK;
+    }
+    const double target = frac * out->kappa_se;
+    // smallest K > n with A r^K / (1 - r) <= target
+    double K = std::ceil(std::log(target * (1.0 - rr) / A) / std::log(rr));
+    if (!(K >= n + 1)) K = n + 1;
+    out->kmax = (int32_t)std::min<double>(K, (double)kp);
+    out->fit_ok = 1;
+    out->decay = rr;
+    out->amplitude = A;
+    out->bias_bound = A * std::pow(rr, out->kmax) / (1.0 - rr);
     return DMC_OK;
 }

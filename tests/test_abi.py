@@ -52,6 +52,9 @@ def layout_probe(tmp_path_factory):
                     "first_particle"],
         "dmc_stats": ["particles", "scatters", "boundary", "iterations", "capped", "kernel_ms"],
         "dmc_server_opts": ["memory_budget", "max_active", "epoch_flights", "drain_flights", "run"],
+        "dmc_trunc_opts": ["n_pilot", "k_pilot", "bias_fraction"],
+        "dmc_trunc_plan": ["kmax", "k_uncertain", "fit_ok", "n_fit", "decay", "amplitude", "bias_bound", "kappa_se",
+                           "kappa_pilot", "n_pilot"],
         "dmc_tune_trial": ["block", "chunk", "refill_min", "lds_tally", "pilot", "ms", "flights_per_s"],
         "dmc_tune_opts": ["sample_flights", "trial_cap", "use_cache", "trials", "max_trials", "n_trials",
                           "from_cache"],
@@ -121,6 +124,16 @@ def test_autotune_validates_before_device_work():
     best = b.dmc_run_opts()
     assert b.lib().dmc_autotune(None, 0, None, None, C.byref(best)) == b.DMC_E_INVALID
     assert b.lib().dmc_autotune(None, 1, None, None, None) == b.DMC_E_INVALID
+
+
+def test_truncation_planning_validates_before_device_work():
+    j = b.dmc_job()
+    j.source.kind = 0  # wall sources: truncation planning needs the gradient source
+    j.n_particles = 100
+    out = b.dmc_trunc_plan()
+    assert b.lib().dmc_plan_truncation(C.byref(j), None, None, C.byref(out)) == b.DMC_E_INVALID
+    assert b"gradient" in b.lib().dmc_last_error()
+    assert b.lib().dmc_plan_truncation(None, None, None, None) == b.DMC_E_INVALID
 
 
 def test_debug_philox_rejects_null():

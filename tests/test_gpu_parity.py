@@ -246,6 +246,34 @@ def test_autotuner_choice_is_valid_cached_and_result_invariant():
         assert rel_diff(tuned.raw(j), ref.raw(j)) <= 1e-12, j
 
 
+def test_truncation_plan_bounds_the_bias():
+    """Periodic pore cell: the planned K_max cuts a tail whose effect on kappa is
+    within the planned bound plus noise; films need one event (first-event
+    termination is exact there)."""
+    si = di.silicon_like()
+    mat = b.Material(si)
+    job = di.pore_cell(100e-9, 0.3, 1_000_000, seed=601, material=si, kmax=200, n_hj=0)
+    plan = b.plan_truncation(job, material=mat, n_pilot=1_000_000, k_pilot=200)
+    print("pore plan", plan, flush=True)
+    assert plan["fit_ok"] == 1 and plan["n_fit"] >= 3 and 0.0 < plan["decay"] < 1.0
+    K = plan["kmax"]
+    # the bias criterion is stricter than the paper's term-by-term one
+    assert plan["n_fit"] < K < 200 and 1 <= plan["k_uncertain"] <= K
+    assert plan["bias_bound"] <= 0.2 * plan["kappa_se"] * 1.0001
+    long_run = b.simulate([job], material=mat)  # same particles, 200 events
+    job.tally.kmax = K
+    short = b.simulate([job], material=mat)
+    k200, se200 = long_run.read(0, b.Q_KAPPA)
+    kK, seK = short.read(0, b.Q_KAPPA)
+    # same random numbers up to event K: the difference is the discarded tail
+    assert abs(kK[0] - k200[0]) <= plan["bias_bound"] + 3.0 * se200[0], (kK, k200, plan)
+    assert short.stats(0).iterations < long_run.stats(0).iterations
+    film = di.in_plane_film(60e-9, 0.5, 200_000, seed=602, material=si, kmax=100, n_hj=0)
+    fplan = b.plan_truncation(film, material=mat, n_pilot=100_000, k_pilot=100)
+    print("film plan", fplan, flush=True)
+    assert fplan["kmax"] <= 3
+
+
 def small_spot_job():
     from gpu_cases import small_spot
     return small_spot(n=2000, seed=406, grid=8, n_times=4)
