@@ -170,6 +170,9 @@ class Tally:
     grid_lo: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     grid_hi: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     first_event: bool = False  # in-plane films: end at the first scattering event or diffuse reflection
+    # transient jobs: time-windowed track-length temperature and z heat flux in the
+    # z-aligned cylinder (cx, cy, radius, z_lo, z_hi), windows between snapshot times
+    region: Optional[Tuple[float, float, float, float, float]] = None
 
 
 @dataclass

@@ -69,6 +69,8 @@ class Problem(C.Structure):
         ("grid", C.c_int32 * 3), ("grid_lo", C.c_double * 3), ("grid_hi", C.c_double * 3),
         ("seed", C.c_uint64),
         ("first_event", C.c_int32),
+        ("region_kind", C.c_int32), ("region_c", C.c_double * 2), ("region_r", C.c_double),
+        ("region_z", C.c_double * 2),
     ]
 
 
@@ -287,6 +289,14 @@ def prepare(job: di.Job) -> Prepared:
         P.grid[d] = int(tl.grid[d]) if not steady else 0
         P.grid_lo[d], P.grid_hi[d] = float(tl.grid_lo[d]), float(tl.grid_hi[d])
     P.seed = int(job.seed)
+    rg = getattr(tl, "region", None)
+    if rg is not None:
+        if steady:
+            raise ValueError("the windowed region tally needs snapshot times")
+        P.region_kind = 1
+        P.region_c[0], P.region_c[1] = float(rg[0]), float(rg[1])
+        P.region_r = float(rg[2])
+        P.region_z[0], P.region_z[1] = float(rg[3]), float(rg[4])
     size = int(lib().oracle_tally_size(C.byref(P)))
     return Prepared(job, P, keep, C_tot, G_tau, G_v, power, steady, avg_volume, size)
 
@@ -348,6 +358,8 @@ def split_raw(prep: Prepared, raw: np.ndarray) -> Dict[str, np.ndarray]:
     ncell = int(np.prod(tl.grid)) if nt else 0
     out["snap"] = raw[o:o + nt * (ncell + 1)].reshape(nt, ncell + 1); o += nt * (ncell + 1)
     out["snap_abs"] = raw[o:o + nt * (ncell + 1)].reshape(nt, ncell + 1); o += nt * (ncell + 1)
+    if getattr(tl, "region", None) is not None and nt:
+        out["region"] = raw[o:o + 4 * nt].reshape(nt, 4); o += 4 * nt
     return out
 
 
@@ -407,6 +419,19 @@ def finalize(prep: Prepared, raw: np.ndarray, N: Optional[int] = None) -> Dict[s
         res["snap_T_se"] = e_eff * N * np.sqrt(var[:, :-1] / N) / (vcell * prep.C_tot)
         res["snap_overflow"] = S[:, -1]
         res["snap_sum"] = S.sum(axis=1)
+        if "region" in parts:
+            # time average over window [t_{j-1}, t_j): E_eff sum_i s_i (time in R) / (T_w mu(R) C_tot);
+            # heat flux E_eff sum_i s_i (z displacement in R) / (T_w mu(R)); per-particle moments for SE
+            rg = tl.region
+            mu = math.pi * rg[2] ** 2 * (rg[4] - rg[3])
+            edges = np.concatenate([[0.0], np.asarray(tl.times, dtype=np.float64)])
+            tw = np.diff(edges)
+            R = parts["region"]
+            for key, col, den in (("region_T", 0, mu * prep.C_tot), ("region_q", 2, mu)):
+                m = R[:, col] / N
+                v = np.maximum(R[:, col + 1] / N - m * m, 0.0) * N / max(N - 1, 1)
+                res[key] = e_eff * R[:, col] / (tw * den)
+                res[key + "_se"] = e_eff * np.sqrt(N * v) / (tw * den)
     return res
 
 

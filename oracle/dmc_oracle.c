@@ -309,6 +309,11 @@ typedef struct {
     /* in-plane film: end a trajectory at its first scattering event or first
      * diffuse wall reflection (the flux carried afterwards averages to zero) */
     int32_t first_event;
+    /* time-windowed track-length tally in a z-aligned cylinder (transient jobs):
+     * region_kind 1 = {(x-cx)^2 + (y-cy)^2 < R^2, zlo <= z < zhi}; windows
+     * [0, t_0), [t_0, t_1), ... [t_{n-2}, t_{n-1}) from the snapshot times */
+    int32_t region_kind;
+    double region_c[2], region_r, region_z[2];
 } oracle_problem;
 
 typedef struct {
@@ -316,7 +321,7 @@ typedef struct {
 } oracle_counters;
 
 /* offsets of the tally sections inside the flat FP64 output buffer */
-typedef struct { size_t bins, kappa, hj, snap, snap_abs, total; int64_t ncell; } tally_layout;
+typedef struct { size_t bins, kappa, hj, snap, snap_abs, region, total; int64_t ncell; } tally_layout;
 
 static tally_layout layout_of(const oracle_problem *P)
 {
@@ -328,6 +333,9 @@ static tally_layout layout_of(const oracle_problem *P)
     t.ncell = (int64_t)P->grid[0] * P->grid[1] * P->grid[2];
     t.snap = o; o += (size_t)P->n_times * (size_t)(t.ncell + 1);
     t.snap_abs = o; o += (size_t)P->n_times * (size_t)(t.ncell + 1);
+    /* per window: sum of each particle's s * (time in region), its square, the
+     * same for s * (z displacement in region) */
+    t.region = o; o += (P->region_kind && P->n_times > 0) ? (size_t)4 * (size_t)P->n_times : 0;
     t.total = o;
     return t;
 }
@@ -590,6 +598,61 @@ static void score_snapshots(const oracle_problem *P, double *snap, double *snap_
     }
 }
 
+/* Time-averaged estimator (the sampling of the steady-state paragraph applied
+ * over a finite window): the part [u0, u1] of the segment x + v Omega u,
+ * u in [0, seg], that lies in the region; returns 0 if there is none. */
+static int region_interval(const oracle_problem *P, const particle *p, double v, double seg, double *u0, double *u1)
+{
+    double lo = 0.0, hi = seg;
+    /* the slab zlo <= z < zhi */
+    double wz = v * p->o[2];
+    if (wz == 0.0) {
+        if (!(p->x[2] >= P->region_z[0] && p->x[2] < P->region_z[1])) return 0;
+    } else {
+        double ta = (P->region_z[0] - p->x[2]) / wz, tb = (P->region_z[1] - p->x[2]) / wz;
+        if (ta > tb) { double s = ta; ta = tb; tb = s; }
+        if (ta > lo) lo = ta;
+        if (tb < hi) hi = tb;
+    }
+    /* the cylinder (x - cx)^2 + (y - cy)^2 < R^2 */
+    double wx = v * p->o[0], wy = v * p->o[1];
+    double dx = p->x[0] - P->region_c[0], dy = p->x[1] - P->region_c[1];
+    double a = wx * wx + wy * wy, b = dx * wx + dy * wy, cc = dx * dx + dy * dy - P->region_r * P->region_r;
+    if (a == 0.0) {
+        if (!(cc < 0.0)) return 0;
+    } else {
+        double disc = b * b - a * cc;
+        if (!(disc > 0.0)) return 0;
+        double sq = sqrt(disc);
+        double ta = (-b - sq) / a, tb = (-b + sq) / a;
+        if (ta > lo) lo = ta;
+        if (tb < hi) hi = tb;
+    }
+    if (!(hi > lo)) return 0;
+    *u0 = lo;
+    *u1 = hi;
+    return 1;
+}
+
+/* Adds s * (time in region) and s * (z displacement in region) of a segment
+ * starting at time ta to the particle's per-window sums rt, rq. */
+static void score_region(const oracle_problem *P, double *rt, double *rq, const particle *p, double v, double ta,
+                         double seg)
+{
+    double u0, u1;
+    if (!region_interval(P, p, v, seg, &u0, &u1)) return;
+    double a = ta + u0, b = ta + u1, w0 = 0.0;
+    for (int32_t j = 0; j < P->n_times; ++j) {
+        double w1 = P->times[j];
+        double lo = (a > w0) ? a : w0, hi = (b < w1) ? b : w1;
+        if (hi > lo) {
+            rt[j] += p->s * (hi - lo);
+            rq[j] += p->s * v * p->o[2] * (hi - lo);
+        }
+        w0 = w1;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Steps I-VI for particles pid0 .. pid1-1                                  */
 /* ------------------------------------------------------------------------ */
@@ -605,6 +668,9 @@ int oracle_run(const oracle_problem *P, uint64_t pid0, uint64_t pid1, double *ta
     int transient = P->n_times > 0;
     double t_final = transient ? P->times[P->n_times - 1] : INFINITY;
     double *h = (P->n_hj > 0) ? (double *)calloc((size_t)P->n_hj, sizeof(double)) : NULL;
+    int region = P->region_kind && transient;
+    double *rt = region ? (double *)calloc((size_t)P->n_times, sizeof(double)) : NULL;
+    double *rq = region ? (double *)calloc((size_t)P->n_times, sizeof(double)) : NULL;
     for (uint64_t pid = pid0; pid < pid1; ++pid) {
         particle p;
         emit(P, pid, &p);                                             /* step I */
@@ -612,6 +678,10 @@ int oracle_run(const oracle_problem *P, uint64_t pid0, uint64_t pid1, double *ta
         double t = 0.0, Lz = 0.0;
         uint32_t k = 0, nscat = 0;
         if (h) memset(h, 0, (size_t)P->n_hj * sizeof(double));
+        if (region) {
+            memset(rt, 0, (size_t)P->n_times * sizeof(double));
+            memset(rq, 0, (size_t)P->n_times * sizeof(double));
+        }
         cnt->particles++;
         for (;;) {
             uint32_t w[4];
@@ -630,6 +700,7 @@ int oracle_run(const oracle_problem *P, uint64_t pid0, uint64_t pid1, double *ta
             Lz += dz;
             if (h && nscat < (uint32_t)P->n_hj) h[nscat] += dz;
             if (transient) score_snapshots(P, tally + lay.snap, tally + lay.snap_abs, lay.ncell, &p, v, t, seg);
+            if (region) score_region(P, rt, rq, &p, v, t, seg);
             double t_new = t + seg;
             if (transient && t_new > t_final) break;                 /* step VI */
             /* move */
@@ -660,9 +731,18 @@ int oracle_run(const oracle_problem *P, uint64_t pid0, uint64_t pid1, double *ta
             tally[lay.hj + j] += h[j];
             tally[lay.hj + P->n_hj + j] += h[j] * h[j];
         }
+        for (int32_t j = 0; region && j < P->n_times; ++j) {
+            double *r = tally + lay.region + 4 * (size_t)j;
+            r[0] += rt[j];
+            r[1] += rt[j] * rt[j];
+            r[2] += rq[j];
+            r[3] += rq[j] * rq[j];
+        }
         if (nscat_out) nscat_out[pid - pid0] = nscat;
     }
     free(h);
+    free(rt);
+    free(rq);
     return 0;
 }
 

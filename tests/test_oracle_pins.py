@@ -392,3 +392,83 @@ def test_film_flux_after_first_event_vanishes():
     assert np.all(np.abs(hj[1:]) <= 4 * se[1:])
     assert abs(hj.sum() - res["kappa"]) <= 1e-9 * abs(res["kappa"])
     assert hj[0] > 10 * se[0]
+
+
+# ------------------------------------------- time-windowed region tally ----
+
+def _spot(mat, n, seed, times, region, specularity=0.0):
+    job = di.heated_spot(n=n, seed=seed, material=mat, grid=4, n_times=len(times), specularity=specularity)
+    job.tally.times = tuple(times)
+    job.tally.region = region
+    return job
+
+
+def test_region_tally_conserves_energy():
+    """A region holding every particle at every time: the windowed temperature is
+    the total deviational energy over C_tot mu(R), in every window, exactly."""
+    mat = di.silicon_like()
+    times = (1e-12, 1e-11, 5e-11)
+    job = _spot(mat, 2000, 51, times, (0.0, 0.0, 1.0, 0.0, 1.0))
+    res, *_ = oracle.simulate(job, threads=4)
+    mu = math.pi * 1.0 * 1.0
+    exact = 1.0 * math.pi ** 1.5 * (1e-6) ** 3 / 2.0 / mu  # dT pi^{3/2} r0^3 / 2 / mu
+    assert np.allclose(res["region_T"], exact, rtol=1e-12, atol=0.0), (res["region_T"], exact)
+    assert np.all(res["region_T_se"] <= 1e-6 * exact)  # every particle contributes the same
+
+
+def _ballistic_region_reference(v, r0, dT, times, region, nq=24):
+    """Ballistic transport (no scattering) from the Gaussian initial condition with
+    a specular surface, i.e. the full-space problem with the mirrored Gaussian:
+    dT(x, t) is the mean of dT exp(-|y|^2/r0^2) over the sphere |y - x| = v t, and
+    q_z(x, t) = C v <Omega_z dT exp(-|x - v t Omega|^2/r0^2)> over directions.
+    Averages over the cylinder and each window by Gauss-Legendre quadrature.
+    Returns (T, q / C) per window."""
+    cx, cy, R, zlo, zhi = region
+    xg, wg = np.polynomial.legendre.leggauss(nq)
+    rho = 0.5 * R * (xg + 1.0); wr = 0.5 * R * wg * 2.0 * np.pi * rho
+    zz = zlo + 0.5 * (zhi - zlo) * (xg + 1.0); wz = 0.5 * (zhi - zlo) * wg
+    mu_d, wmu = np.polynomial.legendre.leggauss(32)
+    nphi = 32
+    phi = (np.arange(nphi) + 0.5) * 2.0 * np.pi / nphi
+    vol = math.pi * R * R * (zhi - zlo)
+    edges = np.concatenate([[0.0], times])
+    T_out, Q_out = [], []
+    for a, b in zip(edges[:-1], edges[1:]):
+        tg = a + 0.5 * (b - a) * (xg + 1.0); wt = 0.5 * (b - a) * wg
+        Tw = Qw = 0.0
+        for t, w_t in zip(tg, wt):
+            s = v * t
+            for r_, w_r in zip(rho, wr):
+                for z_, w_z in zip(zz, wz):
+                    # point (r_, 0, z_): average over directions Omega = (sin th cos phi, sin th sin phi, cos th)
+                    st = np.sqrt(1.0 - mu_d ** 2)
+                    ox = st[:, None] * np.cos(phi)[None, :]
+                    oz = np.broadcast_to(mu_d[:, None], ox.shape)
+                    d2 = (r_ - s * ox) ** 2 + (s * st[:, None] * np.sin(phi)[None, :]) ** 2 + (z_ - s * oz) ** 2
+                    g = dT * np.exp(-d2 / r0 ** 2)
+                    wdir = (wmu[:, None] / 2.0) * (1.0 / nphi)
+                    Tw += w_t * w_r * w_z * float(np.sum(wdir * g))
+                    Qw += w_t * w_r * w_z * float(np.sum(wdir * v * oz * g))
+        T_out.append(Tw / (vol * (b - a)))
+        Q_out.append(Qw / (vol * (b - a)))
+    return np.array(T_out), np.array(Q_out)
+
+
+def test_region_tally_ballistic_limit():
+    """No scattering before t_final (tau = 1 s) and a specular surface: the windowed
+    temperature and z heat flux in a surface cylinder equal the ballistic solution
+    from the Gaussian initial condition."""
+    v, r0 = 6000.0, 1e-6
+    mat = di.gray_material(vg=v, tau=1.0)
+    times = (5e-11, 1e-10, 1.5e-10, 2.5e-10)
+    region = (0.0, 0.0, 0.3e-6, 0.0, 0.3e-6)
+    job = _spot(mat, 6_000_000, 52, times, region, specularity=1.0)
+    res, *_ = oracle.simulate(job, threads=THREADS)
+    T_ref, Q_ref = _ballistic_region_reference(v, r0, 1.0, np.array(times), region)
+    C_tot = oracle.tabulate(mat)[2][0]
+    # the flux is a difference of opposite streams, so its relative error is larger
+    for key, ref, teeth in (("region_T", T_ref, 0.005), ("region_q", C_tot * Q_ref, 0.08)):
+        got, se = res[key], res[key + "_se"]
+        assert np.all(se < teeth * np.abs(ref)), (key, se, ref)
+        assert np.all(np.abs(got - ref) <= 4.0 * se + 2e-3 * np.abs(ref)), (key, got, ref, se)
+    assert np.all(res["region_q"] > 0.0)  # heat flows into the substrate
