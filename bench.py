@@ -111,12 +111,14 @@ def launch_params(jobs, mat, precision="fp32", stream=None, overrides=None, tune
 
 def other_workloads(b, di, mat, mat_in, stream):
     """One autotuned launch each of the transient heated spot (1e9 particles,
-    64^3 grid x 50 times), of the 64 batched nanostructures (1e6-1e8 particles
+    64^3 grid x 50 times, and the windowed tally in a 10 um x 5 nm surface
+    cylinder like a thermoreflectance probe), of the 64 batched nanostructures (1e6-1e8 particles
     each, K_max = 40), and of the same batch with first-event termination for
     its 24 films (exact for films), after the tuner's trials have loaded the
     kernels.  Reported beside the headline, not in it."""
     res = {}
-    for name, jobs in (("heated_spot_1e9_64cube_50times", [di.heated_spot(material=mat_in)]),
+    for name, jobs in (("heated_spot_1e9_64cube_50times_ttr_probe",
+                        [di.heated_spot(material=mat_in, probe=di.TTR_PROBE)]),
                        ("nanostructures_64_instances", di.batched_nanostructures(material=mat_in)),
                        ("nanostructures_64_instances_first_event_films",
                         di.batched_nanostructures(material=mat_in, first_event_films=True))):
@@ -129,6 +131,9 @@ def other_workloads(b, di, mat, mat_in, stream):
         sc = sum(s.scatters for s in st)
         fl = sum(s.iterations for s in st)
         parts = sum(s.particles for s in st)
+        if jobs[0].tally.region is not None:
+            T, Tse = r.read(0, b.Q_REGION_T)
+            res["ttr_probe_T_windows_10_20_30_40_49"] = [[float(T[i]), float(Tse[i])] for i in (10, 20, 30, 40, 49)]
         res[name] = {"scattering_events_per_s": sc / (ms / 1e3), "particles_per_s": parts / (ms / 1e3),
                      "flights_per_s": fl / (ms / 1e3), "kernel_ms": ms, "particles": parts, "scattering_events": sc,
                      "capped": sum(s.capped for s in st), "launch": params, "autotune_s": tune_s}

@@ -221,20 +221,24 @@ def cross_plane_films(n_per_film: int = 100_000_000, n_films: int = 12, n_bins: 
             for j, L in enumerate(film_thicknesses(n_films))]
 
 
+TTR_PROBE = (0.0, 0.0, 10e-6, 0.0, 5e-9)  # surface cylinder of radius 10 um, 5 nm deep
+
+
 def heated_spot(n: int = 1_000_000_000, seed: int = 7, material: Optional[Material] = None,
                 grid: int = 64, n_times: int = 50, r0: float = 1e-6, dT: float = 1.0,
-                specularity: float = 0.0) -> Job:
+                specularity: float = 0.0, probe: Optional[Tuple[float, float, float, float, float]] = None) -> Job:
     """Transient heated spot on a semi-infinite substrate.
 
     Gaussian initial temperature of radius r0 and amplitude dT at the origin of the
     adiabatic surface z = 0; snapshot grid x, y in [-4, 4] um, z in [0, 8] um;
-    times log-spaced 1 ps .. 10 ns (both ends included).
+    times log-spaced 1 ps .. 10 ns (both ends included).  ``probe`` adds the
+    windowed track-length tally in a surface cylinder (e.g. TTR_PROBE).
     """
     mat = material or silicon_like()
     times = tuple(float(t) for t in 10.0 ** (-12.0 + 4.0 * np.arange(n_times) / (n_times - 1)))
     geom = Geometry("halfspace_z", walls=[Wall("adiabatic", specularity=specularity)])
     tally = Tally(n_bins=0, times=times, grid=(grid, grid, grid),
-                  grid_lo=(-4e-6, -4e-6, 0.0), grid_hi=(4e-6, 4e-6, 8e-6))
+                  grid_lo=(-4e-6, -4e-6, 0.0), grid_hi=(4e-6, 4e-6, 8e-6), region=probe)
     return Job(mat, geom, Source("gaussian", dT=dT, radius=r0), tally, int(n), int(seed), "heated_spot")
 
 

@@ -148,7 +148,16 @@ typedef struct {
                             isotropic or Lambertian about the wall normal and the film is
                             invariant along z, so the flux still to come averages to zero.
                             Specular reflections continue the free path.  Rejected elsewhere. */
-    int32_t pad0;
+    int32_t region;      /* transient jobs: 1 adds time-windowed track-length tallies in the
+                            z-aligned cylinder {(x-cx)^2 + (y-cy)^2 < radius^2, z_lo <= z < z_hi}
+                            (a probe region such as a thermoreflectance spot): over each window
+                            [t_{j-1}, t_j) between snapshot times (t_{-1} = 0), the mean
+                            temperature (time spent in the region) and z heat flux (signed
+                            z length travelled in it); the time average of Eq. (3), read as
+                            DMC_Q_REGION_T / DMC_Q_REGION_QZ.  0 = none. */
+    double region_c[2];  /* cx, cy [m] */
+    double region_radius;
+    double region_z[2];  /* z_lo, z_hi [m], 0 <= z_lo < z_hi */
 } dmc_tally_desc;
 
 /* ------------------------------------------------------------------------ */
@@ -310,6 +319,8 @@ dmc_status dmc_plan_truncation(const dmc_job *job, const dmc_run_opts *opts, con
 #define DMC_Q_SNAPSHOT 5   /* T - T_eq per grid cell at time_index [K] (n = cells, x fastest) */
 #define DMC_Q_SNAPSHOT_SUM 6 /* raw sum of signs per cell at time_index, overflow last (n = cells+1) */
 #define DMC_Q_RAW 7        /* the job's raw FP64 tally block (n = dmc_tally_raw_size) */
+#define DMC_Q_REGION_T 8   /* windowed mean T - T_eq in the region, one per window [K] (n = n_times) */
+#define DMC_Q_REGION_QZ 9  /* windowed mean z heat flux in the region [W/m^2] (n = n_times) */
 
 /* Waits for the launch, then writes n values of `quantity` of job `job` (and,
  * if stderr_out is not NULL, their standard errors: batch means for bins,

@@ -23,7 +23,7 @@ WALL = {"isothermal": 0, "adiabatic": 1, "periodic": 2}
 SRC = {"walls": 0, "gaussian": 1, "gradient": 2}
 PREC = {"fp64": 0, "fp32": 1}
 FORM = {"plain": 0, "persistent": 1}
-Q_T, Q_TLOC, Q_FLUX, Q_KAPPA, Q_HJ, Q_SNAPSHOT, Q_SNAPSHOT_SUM, Q_RAW = range(8)
+Q_T, Q_TLOC, Q_FLUX, Q_KAPPA, Q_HJ, Q_SNAPSHOT, Q_SNAPSHOT_SUM, Q_RAW, Q_REGION_T, Q_REGION_QZ = range(10)
 TABLE_GAIN, TABLE_INIT, TABLE_FLUX = 0, 1, 2
 
 f64p = C.POINTER(C.c_double)
@@ -50,7 +50,8 @@ class dmc_source(C.Structure):
 class dmc_tally_desc(C.Structure):
     _fields_ = [("n_bins", C.c_int32), ("n_batches", C.c_int32), ("kmax", C.c_int32), ("n_hj", C.c_int32),
                 ("grid", C.c_int32 * 3), ("grid_lo", C.c_double * 3), ("grid_hi", C.c_double * 3),
-                ("first_event", C.c_int32), ("pad0", C.c_int32)]
+                ("first_event", C.c_int32), ("region", C.c_int32), ("region_c", C.c_double * 2),
+                ("region_radius", C.c_double), ("region_z", C.c_double * 2)]
 
 
 class dmc_run_opts(C.Structure):
@@ -358,6 +359,12 @@ def job_struct(job, material: Material, keep: list) -> dmc_job:
     td = dmc_tally_desc()
     td.n_bins, td.n_batches, td.kmax, td.n_hj = int(t.n_bins), int(t.n_batches), int(t.kmax), int(t.n_hj)
     td.first_event = int(bool(getattr(t, "first_event", False)))
+    rg = getattr(t, "region", None)
+    if rg is not None:
+        td.region = 1
+        td.region_c[0], td.region_c[1] = float(rg[0]), float(rg[1])
+        td.region_radius = float(rg[2])
+        td.region_z[0], td.region_z[1] = float(rg[3]), float(rg[4])
     for i in range(3):
         td.grid[i] = int(t.grid[i])
         td.grid_lo[i] = float(t.grid_lo[i])
@@ -425,6 +432,8 @@ class Result:
                 n = int(np.prod(jb.tally.grid))
             elif quantity == Q_SNAPSHOT_SUM:
                 n = int(np.prod(jb.tally.grid)) + 1
+            elif quantity in (Q_REGION_T, Q_REGION_QZ):
+                n = len(jb.tally.times)
             else:
                 raise ValueError("give n for this quantity")
         mean = np.zeros(max(n, 1))

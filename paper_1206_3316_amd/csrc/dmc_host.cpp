@@ -200,8 +200,8 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
     d.n_hj = t.n_hj;
     d.n_times = jb.n_times;
     d.lds_bins = d.lds_kappa = d.lds_hj = -1;
-    d.off_bins = d.off_kappa = d.off_hj = d.off_snap = d.off_snap_abs = d.off_dispx = -1;
-    d.lds_dispx = -1;
+    d.off_bins = d.off_kappa = d.off_hj = d.off_snap = d.off_snap_abs = d.off_dispx = d.off_region = -1;
+    d.lds_dispx = d.lds_region = -1;
     d.disp_tel = 0;
     if ((g.kind == DMC_GEOM_SLAB_Z || g.kind == DMC_GEOM_FILM_X) && t.n_bins > 0) {
         d.bins_per_len = (double)t.n_bins / g.length;
@@ -296,6 +296,19 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
         // a Gaussian initial condition gives every particle the sign of dT, so
         // sum |s| = |sum s| per cell: the device skips that second atomic
         d.snap_abs_on = (s.kind == DMC_SRC_GAUSSIAN) ? 0 : 1;
+    }
+    if (t.region) {
+        if (!transient || t.region != 1) return fail(DMC_E_INVALID, "the region tally needs snapshot times");
+        if (!finite_pos(t.region_radius) || !finite_nonneg(t.region_z[0]) || !std::isfinite(t.region_z[1]) ||
+            !(t.region_z[1] > t.region_z[0]) || !std::isfinite(t.region_c[0]) || !std::isfinite(t.region_c[1]))
+            return fail(DMC_E_INVALID, "region: radius > 0, 0 <= z_lo < z_hi, finite centre");
+        d.off_region = o;
+        o += 4 * (int64_t)jb.n_times;
+        d.region_c[0] = t.region_c[0];
+        d.region_c[1] = t.region_c[1];
+        d.region_r = t.region_radius;
+        d.region_z[0] = t.region_z[0];
+        d.region_z[1] = t.region_z[1];
     }
     if (t.n_bins > 0) {  // last: the visible block stays contiguous
         // hidden: not part of the raw block a caller reads (the host folds it into
@@ -412,7 +425,7 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
     if (b.n_resume && !b.drain_iters) return fail(DMC_E_INVALID, "resuming needs a time-bounded launch");
     const size_t stats_lds = a.lds_stats ? (size_t)n_jobs * kStats * 8 : 0;
     for (auto &d : devs) {
-        d.lds_bins = d.lds_kappa = d.lds_hj = d.lds_dispx = -1;
+        d.lds_bins = d.lds_kappa = d.lds_hj = d.lds_dispx = d.lds_region = -1;
         d.disp_tel = (o.form == DMC_FORM_PERSISTENT && spec == GEOM_SLAB && !(b.drain_iters || b.n_resume)) ? 1 : 0;
     }
     int block = 256, grid = 1;
@@ -445,6 +458,10 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
                 if (d.off_hj >= 0 && (size_t)(lo + 2 * d.n_hj) <= budget) {
                     d.lds_hj = lo;
                     lo += 2 * d.n_hj;
+                }
+                if (d.off_region >= 0 && (size_t)(lo + 4 * d.n_times) <= budget) {
+                    d.lds_region = lo;
+                    lo += 4 * d.n_times;
                 }
             }
         }
@@ -589,6 +606,7 @@ dmc_status gather_jobs(const dmc_job *jobs, int32_t n_jobs, std::vector<JobHost>
         if (d.off_snap >= 0) d.off_snap += toff;
         if (d.off_snap_abs >= 0) d.off_snap_abs += toff;
         if (d.off_dispx >= 0) d.off_dispx += toff;
+        if (d.off_region >= 0) d.off_region += toff;
         toff += jh[i].size;
         d.times_off = (int32_t)tim;
         tim += (int64_t)jh[i].times.size();
@@ -947,6 +965,29 @@ extern "C" dmc_status dmc_tally_read(const dmc_result *cres, int32_t job, int32_
                 const double m = S[c] / N;
                 const double var = std::max(A[c] / N - m * m, 0.0);
                 se[c] = sc * std::sqrt(N * var);
+            }
+        }
+        return DMC_OK;
+    }
+    if (q == DMC_Q_REGION_T || q == DMC_Q_REGION_QZ) {
+        // time average over window [t_{j-1}, t_j): E_eff sum_i s_i (time in R) / (T_w mu(R) C_tot),
+        // z heat flux E_eff sum_i s_i (z length in R) / (T_w mu(R)); per-particle moments for the SE
+        if (d.off_region < 0) return fail(DMC_E_INVALID, "no region tallied");
+        if (n < (size_t)d.n_times) return fail(DMC_E_INVALID, "output too small");
+        const double mu = M_PI * d.region_r * d.region_r * (d.region_z[1] - d.region_z[0]);
+        const double e_eff = h.power / N;
+        const int col = (q == DMC_Q_REGION_T) ? 0 : 2;
+        const double den = (q == DMC_Q_REGION_T) ? mu * M.C_tot : mu;
+        double w0 = 0.0;
+        for (int j = 0; j < d.n_times; ++j) {
+            const double tw = h.times[j] - w0;
+            w0 = h.times[j];
+            const double s1 = T[d.off_region + 4 * j + col], s2 = T[d.off_region + 4 * j + col + 1];
+            mean[j] = e_eff * s1 / (tw * den);
+            if (se) {
+                const double m = s1 / N;
+                const double var = std::max(s2 / N - m * m, 0.0) * N / std::max(N - 1.0, 1.0);
+                se[j] = e_eff * std::sqrt(N * var) / (tw * den);
             }
         }
         return DMC_OK;

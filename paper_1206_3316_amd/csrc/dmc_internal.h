@@ -56,7 +56,9 @@ struct alignas(16) JobDev {
     int32_t lds_dispx;      // -1: in global memory
     int32_t disp_tel;       // 1: the displacement is telescoped (persistent slab kernel)
     int32_t first_event;    // 1: a diffuse wall reflection (or the first scattering event) ends the particle
-    int32_t pad2;
+    int32_t lds_region;     // -1: in global memory
+    int64_t off_region;     // windowed region tally [n_times][4]: sum v_T, v_T^2, v_Q, v_Q^2 (-1: none)
+    double region_c[2], region_r, region_z[2];
 };
 
 // A particle suspended at the end of a time-bounded launch (serving epochs):
@@ -67,7 +69,10 @@ struct alignas(16) Suspended {
     uint64_t pid;
     uint32_t k, nscat, nbound, m;
     int32_t last, tcur, slot, sign;
+    double rt, rq;          // region tally sums of the current window
+    int32_t rwin, pad[3];
 };
+static_assert(sizeof(Suspended) == 144, "Suspended layout");
 
 struct KArgs {
     const JobDev *jobs;

@@ -207,6 +207,11 @@ struct Lane {
     double d0, d1, d2;      // entry B: the bin it came from
     int32_t tcur;
     double tnext, tend;  // next snapshot time and final time (+inf when steady)
+    // windowed region tally: top of the region (-inf without one), the window
+    // whose sums the particle is accumulating (-1: none) and those sums
+    R rzhi;
+    int32_t rwin;
+    double rt, rq;
 };
 
 struct Shared {
@@ -324,6 +329,9 @@ __device__ __forceinline__ void bind_job(Lane<R> &p, const JobDev &J, uint64_t p
     p.bw = (R)J.bin_width;
     p.key0 = J.key0;
     p.key1 = J.key1;
+    p.rzhi = (J.off_region >= 0 && (G == GEOM_HALF || G == GEOM_ANY)) ? (R)J.region_z[1] : -Pr<R>::inf();
+    p.rwin = -1;
+    p.rt = p.rq = 0.0;
     {
         const int32_t boff = p.batch * 3 * p.n_bins;
         p.bl = (J.lds_bins >= 0) ? J.lds_bins + boff : -1;
@@ -623,6 +631,77 @@ __device__ void score_snapshots(Lane<R> &p, const KArgs &a, const JobDev &J, dou
     p.tnext = (p.tcur < p.n_times) ? times[p.tcur] : __builtin_huge_val();
 }
 
+// Adds the particle's sums of its current region window to the tallies.
+template <typename R>
+__device__ __forceinline__ void region_flush(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J)
+{
+    if (p.rwin < 0) return;
+    const int32_t o = 4 * p.rwin;
+    tadd(a, sh, J.lds_region, J.off_region, o, p.rt);
+    tadd(a, sh, J.lds_region, J.off_region, o + 1, p.rt * p.rt);
+    tadd(a, sh, J.lds_region, J.off_region, o + 2, p.rq);
+    tadd(a, sh, J.lds_region, J.off_region, o + 3, p.rq * p.rq);
+    p.rt = p.rq = 0.0;
+    p.rwin = -1;
+}
+
+// Time average of Eq. (3) over windows [t_{j-1}, t_j) in a z-aligned cylinder:
+// the part [lo, hi] of the segment x + v Omega u, u in [0, seg], inside the
+// region adds s (hi - lo) and s v Omega_z (hi - lo) to the particle's sums of the
+// window(s) it falls in.  Same operations, in the same order, as the FP64
+// reference, so the parity mode agrees.
+template <typename R>
+__device__ void score_region(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, R seg)
+{
+    R lo = (R)0, hi = seg;
+    const R wz = p.v * p.oz;
+    if (wz == (R)0) {
+        if (!(p.z >= (R)J.region_z[0] && p.z < (R)J.region_z[1])) return;
+    } else {
+        R ta = ((R)J.region_z[0] - p.z) / wz, tb = ((R)J.region_z[1] - p.z) / wz;
+        if (ta > tb) {
+            const R s = ta;
+            ta = tb;
+            tb = s;
+        }
+        if (ta > lo) lo = ta;
+        if (tb < hi) hi = tb;
+    }
+    const R wx = p.v * p.ox, wy = p.v * p.oy;
+    const R dx = p.x - (R)J.region_c[0], dy = p.y - (R)J.region_c[1];
+    const R rr = (R)J.region_r;
+    const R A = wx * wx + wy * wy, B = dx * wx + dy * wy, Cc = dx * dx + dy * dy - rr * rr;
+    if (A == (R)0) {
+        if (!(Cc < (R)0)) return;
+    } else {
+        const R disc = B * B - A * Cc;
+        if (!(disc > (R)0)) return;
+        const R sq = Pr<R>::sq(disc);
+        const R ta = (-B - sq) / A, tb = (-B + sq) / A;
+        if (ta > lo) lo = ta;
+        if (tb < hi) hi = tb;
+    }
+    if (!(hi > lo)) return;
+    const double t0 = p.t + (double)lo, t1 = p.t + (double)hi;
+    const double *times = a.times + J.times_off;
+    int j = (p.rwin > 0) ? p.rwin : 0;
+    double w0 = (j == 0) ? 0.0 : times[j - 1];
+    for (; j < p.n_times; ++j) {
+        const double w1 = times[j];
+        const double l = (t0 > w0) ? t0 : w0, h = (t1 < w1) ? t1 : w1;
+        if (h > l) {
+            if (j != p.rwin) {
+                region_flush(p, a, sh, J);
+                p.rwin = j;
+            }
+            p.rt += (double)p.s * (h - l);
+            p.rq += (double)p.s * (double)p.v * (double)p.oz * (h - l);
+        }
+        if (w1 >= t1) break;
+        w0 = w1;
+    }
+}
+
 // ------------------------------------------------------ boundary search ----
 
 // Earliest surface hit time along x + v Omega t, excluding p.last.
@@ -778,6 +857,9 @@ __device__ void suspend(Lane<R> &p, const KArgs &a, const Shared &sh)
     S.tcur = p.tcur;
     S.slot = p.slot;
     S.sign = p.s > (R)0 ? 1 : -1;
+    S.rt = p.rt;
+    S.rq = p.rq;
+    S.rwin = p.rwin;
     if (a.lds_stats)
         atomicAdd(sh.lstats + p.slot * kStats + 5, 1ull);
     else
@@ -807,6 +889,9 @@ __device__ void resume(Lane<R> &p, const KArgs &a, const Shared &sh, uint32_t i)
     p.tcur = S.tcur;
     set_times(p, a, J);
     p.s = (R)S.sign;
+    p.rt = S.rt;
+    p.rq = S.rq;
+    p.rwin = S.rwin;
     load_state(p, a, sh, S.m);
     set_kbin(p);
     p.cbin = (p.n_bins > 0) ? p.kbin : -1;
@@ -818,6 +903,7 @@ template <typename R, int FORM, int G>
 __device__ void finish(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, bool capped)
 {
     if (p.n_bins > 0) bin_flush<R, FORM, G>(p, a, sh);
+    if (G == GEOM_HALF || G == GEOM_ANY) region_flush(p, a, sh, J);
     if (telescoped<FORM, G>() && p.n_bins > 0) {
         // end term of the telescoped displacement: F_k(z_end) for every bin
         const R z = p.z;
@@ -889,6 +975,8 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
     if (G == GEOM_ANY || G == GEOM_HALF) {
         const double tb_abs = p.t + (double)seg;
         if (p.tnext < tb_abs) score_snapshots(p, a, J, (double)seg);
+        // windowed region tally; most segments lie wholly above the region
+        if (fmin(p.z, p.z + p.v * p.oz * seg) < p.rzhi) score_region(p, a, sh, J, seg);
         if (tb_abs > p.tend) return 1;  // step VI
     }
     // move
@@ -999,6 +1087,12 @@ __device__ void flush_shared(const KArgs &a, const Shared &sh)
                 for (int i = threadIdx.x; i < J.n_batches; i += blockDim.x) {
                     const double v = sh.ltally[J.lds_dispx + i];
                     if (v != 0.0) gadd(a.tally + J.off_dispx + i, v);
+                }
+            }
+            if (J.lds_region >= 0) {
+                for (int i = threadIdx.x; i < 4 * J.n_times; i += blockDim.x) {
+                    const double v = sh.ltally[J.lds_region + i];
+                    if (v != 0.0) gadd(a.tally + J.off_region + i, v);
                 }
             }
             if (J.lds_kappa >= 0 && threadIdx.x < 2) {

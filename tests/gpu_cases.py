@@ -15,6 +15,14 @@ def small_spot(n=3000, seed=5, grid=16, n_times=8, t_max=5e-11, mat=None):
     return job
 
 
+def spot_region(n=6000, seed=15):
+    """Heated spot with a windowed surface-cylinder tally (a thermoreflectance-like probe)."""
+    job = small_spot(n=n, seed=seed, grid=8, n_times=6, t_max=2e-10)
+    job.tally.region = (0.0, 0.0, 0.6e-6, 0.0, 0.3e-6)
+    job.name = "spot_region"
+    return job
+
+
 def mixed_slab(n=20000, seed=12, mat=None):
     """Hot isothermal wall at z = 0, partly specular adiabatic wall at z = L."""
     mat = mat or di.gray_material()
@@ -47,6 +55,7 @@ def parity_cases():
                                            specularity=0.7),
         "periodic_film": periodic_slab(),
         "spot": small_spot(),
+        "spot_region": spot_region(),
     }
 
 
@@ -72,6 +81,9 @@ def lib_sections(job, raw):
         o += nt * nc
         out["snap_abs"] = raw[o:o + nt * nc].reshape(nt, nc)
         o += nt * nc
+        if getattr(t, "region", None) is not None:
+            out["region"] = raw[o:o + 4 * nt].reshape(nt, 4)
+            o += 4 * nt
     assert o == raw.shape[0], (o, raw.shape)
     return out
 
@@ -101,6 +113,10 @@ def compare_sections(lib_s, orc_s, rel, vmax=None):
                 if q == 2 and vmax is not None:
                     scale = max(scale, 1e-3 * vmax * np.abs(ref[:, 0, :]).max())
                 worst[f"bins{q}"] = float(d / max(scale, 1e-300))
+        elif k == "region":
+            # per window: time and z length in the region, each with its square
+            for col, name in enumerate(("region_t", "region_t2", "region_q", "region_q2")):
+                worst[name] = rel_diff(v[:, col], ref[:, col])
         elif k in ("kappa", "hj"):
             v2 = np.asarray(v).reshape(2, -1)
             r2 = np.asarray(ref).reshape(2, -1)

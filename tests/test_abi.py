@@ -45,7 +45,8 @@ def layout_probe(tmp_path_factory):
         "dmc_wall": ["type", "temperature", "specularity"],
         "dmc_geometry_desc": ["kind", "length", "radius", "wall"],
         "dmc_source": ["kind", "dT", "radius", "gradient"],
-        "dmc_tally_desc": ["n_bins", "n_batches", "kmax", "n_hj", "grid", "grid_lo", "grid_hi", "first_event"],
+        "dmc_tally_desc": ["n_bins", "n_batches", "kmax", "n_hj", "grid", "grid_lo", "grid_hi", "first_event",
+                           "region", "region_c", "region_radius", "region_z"],
         "dmc_run_opts": ["precision", "form", "stream", "block", "chunk", "refill_min", "lds_tally", "grid_blocks",
                          "workspace", "workspace_bytes", "nscat_out", "prio_flights"],
         "dmc_job": ["material", "geometry", "source", "tally", "n_particles", "seed", "times", "n_times",

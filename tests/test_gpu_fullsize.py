@@ -129,7 +129,7 @@ def test_cross_plane_film_fp64_slices_match_oracle(si, j):
 def test_heated_spot_full_size(si):
     """1e9 particles, 64^3 grid x 50 snapshot times, FP32 flight / FP64 tallies."""
     mat, lm = si
-    job = di.heated_spot(material=mat)
+    job = di.heated_spot(material=mat, probe=di.TTR_PROBE)
     N = job.n_particles
     params = bench.launch_params([job], lm)
     ns = torch.zeros(N, dtype=torch.int32, device="cuda")
@@ -152,6 +152,12 @@ def test_heated_spot_full_size(si):
             assert abs(lo - hi) <= 5.0 * math.sqrt(lo + hi) + 1.0, (ti, axis, lo, hi)
     T, Tse = res.read(0, b.Q_SNAPSHOT, 0)
     assert T.max() > 0.5  # the spot is resolved at 1 ps (dT = 1 K at its centre)
+    # the probe cylinder: resolved, and its windowed temperature falls as the heat
+    # spreads into the substrate
+    Tp, Tpse = res.read(0, b.Q_REGION_T)
+    print("probe T", Tp[::7], Tpse[::7], flush=True)
+    assert np.all(Tpse[20:] < 0.1 * np.abs(Tp[20:]))
+    assert np.all(np.diff(Tp[20:]) < 3.0 * (Tpse[20:][1:] + Tpse[20:][:-1]))
 
 
 def test_heated_spot_fp64_slice_matches_oracle(si):

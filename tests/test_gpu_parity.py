@@ -177,6 +177,10 @@ def test_fp32_production_within_tolerance(name, oracle_runs):
             _assert_stat_close(name, f"snap{ti}", m, se, ores["snap_T"][ti], ores["snap_T_se"][ti])
             s, _ = res.read(0, b.Q_SNAPSHOT_SUM, ti)
             assert s.sum() == job.n_particles  # particles are conserved at every snapshot
+        if getattr(t, "region", None) is not None:
+            for q, key in ((b.Q_REGION_T, "region_T"), (b.Q_REGION_QZ, "region_q")):
+                m, se = res.read(0, q)
+                _assert_stat_close(name, key, m, se, ores[key], ores[key + "_se"])
     st = res.stats(0)
     assert st.particles == job.n_particles and st.capped == 0
 
