@@ -175,21 +175,29 @@ def flights_per_particle(job, sums):
     return 1.5 * job.tally.kmax + 1.0
 
 
-def mix_capacity(b, di, mat, reqs, stream, n_sample=48, n_cap=2_000_000):
-    """Flights/s of the request mix itself: the first n_sample requests, each cut
-    to at most n_cap particles, in one persistent launch (the mix runs the
-    generic kernel, slower than the headline's slab kernel)."""
-    import copy
-    sample = []
+def mix_capacity(b, di, mat, reqs, stream, args, n_sample=64, n_epochs=24):
+    """Device throughput of the request mix when saturated: the first n_sample
+    requests submitted at once to a server, flights / kernel time over epochs
+    3 .. n_epochs (the mix runs the generic kernel in time-bounded epochs)."""
+    free, _ = torch_free_bytes()
+    srv = b.Server(mat, int(min(0.8 * free, 64 << 30)), max_active=32, epoch_flights=args.epoch_flights,
+                   stream=stream, refill_min=4)
     for _, j in reqs[:n_sample]:
-        c = copy.copy(j)
-        c.n_particles = min(j.n_particles, n_cap)
-        sample.append(c)
-    r = b.simulate(sample, material=mat, stream=stream)
-    st = [r.stats(i) for i in range(len(sample))]
-    fl = sum(s.iterations for s in st)
-    r.close()
-    return fl / (st[0].kernel_ms / 1e3)
+        srv.submit(j)
+    f0 = k0 = 0.0
+    for e in range(n_epochs):
+        srv.step()
+        if e == 1:
+            t = srv.totals()
+            f0, k0 = float(t.iterations), float(t.kernel_ms)
+    t = srv.totals()
+    srv.close()
+    return (float(t.iterations) - f0) / ((float(t.kernel_ms) - k0) / 1e3)
+
+
+def torch_free_bytes():
+    import torch
+    return torch.cuda.mem_get_info()
 
 
 def serve(b, di, torch, mat, mat_in, stream, n_requests, args):
@@ -199,7 +207,7 @@ def serve(b, di, torch, mat, mat_in, stream, n_requests, args):
     _, sums = mat.info()
     reqs = di.serving_stream(n_requests, material=mat_in)
     work = [j.n_particles * flights_per_particle(j, sums) for _, j in reqs]
-    capacity = mix_capacity(b, di, mat, reqs, stream)
+    capacity = mix_capacity(b, di, mat, reqs, stream, args)
     rate = 0.8 * capacity / (sum(work) / len(work))
     log(f"serving: mix capacity {capacity:.3e} flights/s, arrival rate {rate:.2f} requests/s")
     arrivals = di.poisson_arrivals(n_requests, rate)

@@ -381,6 +381,10 @@ dmc_status dmc_server_poll(dmc_server *s, uint64_t ticket, int32_t *done);
 dmc_status dmc_server_collect(dmc_server *s, uint64_t ticket, dmc_result **out);
 /* Requests queued / running. */
 dmc_status dmc_server_load(const dmc_server *s, int32_t *queued, int32_t *running);
+/* Counters summed over every epoch run so far (particles finished, scattering
+ * and boundary events, flights, capped; kernel_ms = total epoch kernel time):
+ * flights / kernel_ms is the server's device throughput. */
+dmc_status dmc_server_totals(const dmc_server *s, dmc_stats *out);
 dmc_status dmc_server_destroy(dmc_server *s);
 
 /* ------------------------------------------------------------------------ */

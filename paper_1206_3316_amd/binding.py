@@ -128,6 +128,7 @@ _SIGS = {
     "dmc_server_poll": ([C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)], C.c_int32),
     "dmc_server_collect": ([C.c_void_p, C.c_uint64, C.POINTER(C.c_void_p)], C.c_int32),
     "dmc_server_load": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int32),
+    "dmc_server_totals": ([C.c_void_p, C.POINTER(dmc_stats)], C.c_int32),
     "dmc_server_destroy": ([C.c_void_p], C.c_int32),
     "dmc_debug_philox": ([C.c_uint64, C.POINTER(C.c_uint64), u32p, u32p, u32p, C.c_size_t], C.c_int32),
     "dmc_debug_alias": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int32), u32p, u32p, C.c_size_t], C.c_int32),
@@ -256,6 +257,10 @@ def dmc_server_collect(server, ticket, out):
 
 def dmc_server_load(server, queued, running):
     return _call("dmc_server_load", server, queued, running)
+
+
+def dmc_server_totals(server, out):
+    return _call("dmc_server_totals", server, out)
 
 
 def dmc_server_destroy(server):
@@ -610,6 +615,11 @@ class Server:
         q, r = C.c_int32(), C.c_int32()
         dmc_server_load(self.handle, C.byref(q), C.byref(r))
         return int(q.value), int(r.value)
+
+    def totals(self) -> dmc_stats:
+        out = dmc_stats()
+        dmc_server_totals(self.handle, C.byref(out))
+        return out
 
     def close(self):
         if getattr(self, "handle", None):

@@ -109,6 +109,7 @@ struct dmc_server {
     std::vector<Request *> prev_members;
     int32_t *d_resume_job = nullptr;
     std::vector<int32_t> h_resume_job;
+    dmc_stats totals{};              // all epochs so far
     ~dmc_server()
     {
         if (ev0) (void)hipEventDestroy(ev0);
@@ -305,6 +306,14 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
         r->cursor += devs[i].n;
     }
     S->n_susp = (uint32_t)n_susp;
+    for (size_t i = 0; i < members.size(); ++i) {
+        S->totals.particles += stats[i * kStats + 0];
+        S->totals.scatters += stats[i * kStats + 1];
+        S->totals.boundary += stats[i * kStats + 2];
+        S->totals.iterations += stats[i * kStats + 3];
+        S->totals.capped += stats[i * kStats + 4];
+    }
+    S->totals.kernel_ms += ms;
     S->cur = 1 - S->cur;
     S->prev_members = members;
     for (size_t i = 0; i < S->active.size();) {
@@ -371,6 +380,15 @@ extern "C" dmc_status dmc_server_load(const dmc_server *cs, int32_t *queued, int
     std::lock_guard<std::mutex> g(S->mu);
     if (queued) *queued = (int32_t)S->pending.size();
     if (running) *running = (int32_t)S->active.size();
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_server_totals(const dmc_server *cs, dmc_stats *out)
+{
+    dmc_server *S = const_cast<dmc_server *>(cs);
+    if (!S || !out) return fail(DMC_E_INVALID, "server / out is NULL");
+    std::lock_guard<std::mutex> g(S->mu);
+    *out = S->totals;
     return DMC_OK;
 }
 

@@ -46,12 +46,17 @@ def test_mix_equals_alone_and_requests_join_running_epochs():
         steps += 1
         assert steps < 10_000
     assert steps >= 4  # every request was sliced over several epochs
+    tot = srv.totals()
+    assert tot.particles == sum(j.n_particles for j in reqs) and tot.kernel_ms > 0
+    flights = 0
     for t, job in zip(tickets, reqs):
         res = srv.collect(t)
         solo = b.simulate([job], material=mat)
         assert rel_diff(res.raw(0), solo.raw(0)) <= 1e-12, job.name
         s1, s2 = res.stats(0), solo.stats(0)
         assert (s1.particles, s1.scatters, s1.boundary) == (s2.particles, s2.scatters, s2.boundary), job.name
+        flights += s1.iterations
+    assert tot.iterations == flights  # the server's totals add up its requests' counters
     assert srv.load() == (0, 0)
     srv.close()
 
