@@ -464,9 +464,10 @@ __device__ constexpr bool telescoped()
 }
 
 // Per-lane bin cache (persistent form): entry A holds the sums of the bin the
-// particle is in, entry B those of the bin it came from, so a particle that
-// walks back and forth across one bin edge adds to registers only; an entry is
-// added to the tallies when a third bin displaces it or the particle ends.
+// particle is in; in the slab kernel entry B holds those of the bin it came
+// from, so a particle that walks back and forth across one bin edge adds to
+// registers only.  An entry is added to the tallies when a bin displaces it or
+// the particle ends.
 template <typename R, int FORM, int G>
 __device__ __forceinline__ void flush_entry(Lane<R> &p, const KArgs &a, const Shared &sh, int32_t bin, double &s0,
                                             double &s1, double &s2)
@@ -483,7 +484,7 @@ __device__ __forceinline__ void bin_flush(Lane<R> &p, const KArgs &a, const Shar
 {
     if (FORM != FORM_PERSISTENT) return;  // the plain form adds every contribution directly
     flush_entry<R, FORM, G>(p, a, sh, p.cbin, p.c0, p.c1, p.c2);
-    flush_entry<R, FORM, G>(p, a, sh, p.dbin, p.d0, p.d1, p.d2);
+    if (G == GEOM_SLAB) flush_entry<R, FORM, G>(p, a, sh, p.dbin, p.d0, p.d1, p.d2);
     p.cbin = p.dbin = -1;
 }
 
@@ -492,6 +493,13 @@ template <typename R, int FORM, int G>
 __device__ __forceinline__ void bin_enter(Lane<R> &p, const KArgs &a, const Shared &sh, int32_t k)
 {
     if (k == p.cbin) return;
+    if (G != GEOM_SLAB) {
+        // one entry outside the slab kernel (registers are scarcer in the
+        // general kernels, and bins matter most in thick slabs)
+        flush_entry<R, FORM, G>(p, a, sh, p.cbin, p.c0, p.c1, p.c2);
+        p.cbin = k;
+        return;
+    }
     int32_t tb = p.cbin;
     p.cbin = p.dbin;
     p.dbin = tb;
