@@ -38,19 +38,19 @@ sys.path.insert(0, ROOT)
 # takes 57 lane-slots; v_log_f32 takes 2.
 #   Philox4x32-10 block                                                  57
 #   two word -> uniform conversions (shift, convert, one FMA each)          6
-#   -ln u: log2 (2) and two multiplies; mu = 2u - 1 (2)                     6
+#   flight time (-tau ln2) log2 u: log2 (2), one multiply; mu = 2u - 1      4
 #   wall distance and reciprocal, hit test, segment select                 8
 #   position update                                                        2
 #   end-of-segment bin index (scale, floor, convert, 2 clamps), compare     6
-#   two FP64 tally accumulations, time and time/tau (3 FP32 products,
-#   2 converts, 2 adds); the displacement telescopes along the path          7
+#   two FP64 tally accumulations, time and time/tau (1 FP32 product,
+#   2 converts, 2 adds; the particle's sign multiplies the sums once)      5
 #   gain alias draw (shift, mask, compare, select) + state fetch address    6
-#   flight / scatter counters, truncation and cap tests                    5
+#   flight / scatter counters and the flight-cap test                       4
 # plus 2 for the sign and select logic of the boundary/scatter outcome.  The
 # start bin of a segment is the end bin of the previous one, so one bin index
 # per flight is the minimum; the signed length through a bin depends only on a
 # trajectory's end points, so it costs nothing per flight.
-OPS_PER_FLIGHT = 105
+OPS_PER_FLIGHT = 100
 # HBM traffic of one launch of the timed workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs (profiles/), scaled by the same counters' reading for a plain
 # device copy of known size (bench.py --copy-probe); valid only for the kernel

@@ -269,6 +269,8 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
             d.grid[i] = t.grid[i];
             d.grid_lo[i] = t.grid_lo[i];
             d.grid_ext[i] = t.grid_hi[i] - t.grid_lo[i];
+            d.grid_lof[i] = (float)t.grid_lo[i];
+            d.grid_scf[i] = (float)((double)t.grid[i] / d.grid_ext[i]);
             nc *= t.grid[i];
         }
         if (nc > (int64_t(1) << 31)) return fail(DMC_E_INVALID, "snapshot grid too large");
@@ -370,7 +372,7 @@ int kernel_spec(const JobDev *jobs, int n_jobs)
     for (int i = 0; i < n_jobs; ++i) {
         const JobDev &d = jobs[i];
         if (d.geom != GEOM_SLAB || d.src != SRC_WALLS || d.n_times > 0 || d.wall_type[0] == WALL_PERIODIC ||
-            d.wall_type[1] == WALL_PERIODIC)
+            d.wall_type[1] == WALL_PERIODIC || d.kmax >= 0)
             slab = false;
         if (d.geom != GEOM_HALF || d.src != SRC_GAUSSIAN || d.n_times == 0 || d.n_bins > 0 || d.off_kappa >= 0 ||
             d.n_hj > 0)
@@ -754,7 +756,9 @@ extern "C" dmc_status dmc_material_create(const dmc_branch *br, int32_t nbr, dou
     std::vector<float4> s32(M->K);
     std::vector<double2> s64(M->K);
     for (int m = 0; m < M->K; ++m) {
-        s32[m] = make_float4((float)M->v[m], (float)M->tau[m], (float)(1.0 / M->tau[m]), 0.0f);
+        // v, tau, 1/tau and -tau ln 2 (the flight time is -tau ln2 log2 u)
+        s32[m] = make_float4((float)M->v[m], (float)M->tau[m], (float)(1.0 / M->tau[m]),
+                             (float)(-M->tau[m] * 0.69314718055994530942));
         s64[m] = make_double2(M->v[m], M->tau[m]);
     }
     auto up = [&](void **dst, const void *src, size_t bytes) -> dmc_status {

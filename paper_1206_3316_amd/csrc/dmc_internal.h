@@ -48,6 +48,7 @@ struct alignas(16) JobDev {
     int32_t n_times, times_off;
     int32_t grid[3], pad0;
     double grid_lo[3], grid_ext[3];  // lower bound and extent hi - lo
+    float grid_lof[3], grid_scf[3];  // FP32 lower bound and cells per metre (production form)
     int64_t ncell;
     int32_t stat_slot;      // index of this job's counters (the caller's job index)
     int32_t snap_abs_on;    // 0: every particle has the same sign, the host derives sum|s| = |sum s|

@@ -161,7 +161,7 @@ struct Pr<float> {
     // inside (0, 1), never denormal
     __device__ static float u(uint32_t w) { return fmaf((float)(w >> 9), 1.1920928955078125e-07f, 5.9604644775390625e-08f); }
     // -tau ln u with the hardware log2 (u >= 2^-24, so no range fix-ups are needed)
-    __device__ static float flight(float tau, uint32_t w) { return (tau * -0.693147182f) * __builtin_amdgcn_logf(u(w)); }
+    __device__ static float flight(float ntl, uint32_t w) { return ntl * __builtin_amdgcn_logf(u(w)); }
     __device__ static float sq(float x) { return __builtin_amdgcn_sqrtf(x); }
     // v_sin / v_cos take revolutions: sin(2 pi u) = sin_rev(u)
     __device__ static void cs(uint32_t w, float &c, float &s)
@@ -185,6 +185,7 @@ template <typename R>
 struct Lane {
     R x, y, z, ox, oy, oz;  // position and unit direction
     R v, tau, itau;         // group speed, relaxation time, 1/tau of the current state
+    R ntl;                  // FP32: -tau ln 2 of the current state
     uint32_t m;             // state index
     R s;                    // sign
     int32_t last;           // surface the particle rests on (excluded from the next search)
@@ -212,6 +213,7 @@ struct Lane {
     R rzhi;
     int32_t rwin;
     double rt, rq;
+    double rwbeg, rwend;  // bounds of window rwin
 };
 
 struct Shared {
@@ -232,6 +234,7 @@ __device__ __forceinline__ void load_state<float>(Lane<float> &p, const KArgs &a
     p.v = q.x;
     p.tau = q.y;
     p.itau = q.z;
+    p.ntl = q.w;
 }
 
 template <>
@@ -322,7 +325,7 @@ __device__ __forceinline__ void bind_job(Lane<R> &p, const JobDev &J, uint64_t p
     p.src = J.src;
     p.n_bins = (G == GEOM_HALF || G == GEOM_GRAD) ? 0 : J.n_bins;
     p.n_hj = J.n_hj;
-    p.kmax = J.kmax;
+    p.kmax = (G == GEOM_SLAB) ? -1 : J.kmax;
     p.n_times = (G == GEOM_SLAB || G == GEOM_GRAD) ? 0 : J.n_times;
     p.len = (R)J.length;
     p.bpl = (R)J.bins_per_len;
@@ -473,9 +476,10 @@ __device__ __forceinline__ void flush_entry(Lane<R> &p, const KArgs &a, const Sh
                                             double &s1, double &s2)
 {
     if (bin < 0) return;
-    bins_add<R, FORM>(p, a, sh, bin, s0);
-    bins_add<R, FORM>(p, a, sh, bin + p.n_bins, s1);
-    if (!telescoped<FORM, G>()) bins_add<R, FORM>(p, a, sh, bin + 2 * p.n_bins, s2);
+    const double sg = (double)p.s;  // the entries hold unsigned sums
+    bins_add<R, FORM>(p, a, sh, bin, sg * s0);
+    bins_add<R, FORM>(p, a, sh, bin + p.n_bins, sg * s1);
+    if (!telescoped<FORM, G>()) bins_add<R, FORM>(p, a, sh, bin + 2 * p.n_bins, sg * s2);
     s0 = s1 = s2 = 0.0;
 }
 
@@ -522,14 +526,17 @@ template <typename R, int FORM, int G>
 __device__ __forceinline__ void bin_add(Lane<R> &p, const KArgs &a, const Shared &sh, int k, R t, R vz, bool cached)
 {
     constexpr bool T = telescoped<FORM, G>();
+    if (FORM == FORM_PERSISTENT && cached) {
+        // unsigned sums: the particle's sign multiplies them when they are added
+        p.c0 += (double)t;
+        p.c1 += (double)Pr<R>::ptime(t, p.tau, p.itau);
+        if (!T) p.c2 += (double)(vz * t);
+        return;
+    }
     const double d0 = (double)(p.s * t);
     const double d1 = (double)(p.s * Pr<R>::ptime(t, p.tau, p.itau));
     const double d2 = T ? 0.0 : (double)(p.s * vz * t);
-    if (FORM == FORM_PERSISTENT && cached) {
-        p.c0 += d0;
-        p.c1 += d1;
-        if (!T) p.c2 += d2;
-    } else {
+    {
         bins_add<R, FORM>(p, a, sh, k, d0);
         bins_add<R, FORM>(p, a, sh, k + p.n_bins, d1);
         if (!T) bins_add<R, FORM>(p, a, sh, k + 2 * p.n_bins, d2);
@@ -571,9 +578,9 @@ __device__ void score_bins(Lane<R> &p, const KArgs &a, const Shared &sh, const J
             bin_add<R, FORM, G>(p, a, sh, ka, -((R)nin * tin), vz, true);
         }
         constexpr bool T = telescoped<FORM, G>();
-        const double e0 = (double)(p.s * t1);
-        const double e1 = (double)(p.s * Pr<R>::ptime(t1, p.tau, p.itau));
-        const double e2 = T ? 0.0 : (double)(p.s * vz * t1);
+        const double e0 = (double)t1;  // unsigned, like the cache entries
+        const double e1 = (double)Pr<R>::ptime(t1, p.tau, p.itau);
+        const double e2 = T ? 0.0 : (double)(vz * t1);
         p.c0 -= e0;
         p.c1 -= e1;
         if (!T) p.c2 -= e2;
@@ -616,18 +623,33 @@ __device__ void score_snapshots(Lane<R> &p, const KArgs &a, const JobDev &J, dou
         const double tj = times[p.tcur];
         if (tj >= ta) {
             const double dt = tj - ta;
-            const double pos[3] = {(double)p.x + (double)(p.v * p.ox) * dt, (double)p.y + (double)(p.v * p.oy) * dt,
-                                   (double)p.z + (double)(p.v * p.oz) * dt};
             int64_t idx[3];
             bool inside = true;
-            for (int d = 0; d < 3; ++d) {
-                const double f = (pos[d] - J.grid_lo[d]) / J.grid_ext[d] * (double)J.grid[d];
-                const double fl = floor(f);
-                if (!(fl >= 0.0 && fl < (double)J.grid[d])) {
-                    inside = false;
-                    break;
+            if constexpr (sizeof(R) == 4) {
+                // production: the cell in FP32 with a precomputed scale (no divisions)
+                const float dtf = (float)dt;
+                const float pos[3] = {p.x + (p.v * p.ox) * dtf, p.y + (p.v * p.oy) * dtf, p.z + (p.v * p.oz) * dtf};
+                for (int d = 0; d < 3; ++d) {
+                    const float fl = floorf((pos[d] - J.grid_lof[d]) * J.grid_scf[d]);
+                    if (!(fl >= 0.0f && fl < (float)J.grid[d])) {
+                        inside = false;
+                        break;
+                    }
+                    idx[d] = (int64_t)fl;
                 }
-                idx[d] = (int64_t)fl;
+            } else {
+                // parity: the FP64 reference's operations
+                const double pos[3] = {(double)p.x + (double)(p.v * p.ox) * dt, (double)p.y + (double)(p.v * p.oy) * dt,
+                                       (double)p.z + (double)(p.v * p.oz) * dt};
+                for (int d = 0; d < 3; ++d) {
+                    const double f = (pos[d] - J.grid_lo[d]) / J.grid_ext[d] * (double)J.grid[d];
+                    const double fl = floor(f);
+                    if (!(fl >= 0.0 && fl < (double)J.grid[d])) {
+                        inside = false;
+                        break;
+                    }
+                    idx[d] = (int64_t)fl;
+                }
             }
             const int64_t cell = inside ? (idx[2] * J.grid[1] + idx[1]) * J.grid[0] + idx[0] : J.ncell;
             const int64_t o = (int64_t)p.tcur * (J.ncell + 1) + cell;
@@ -679,18 +701,32 @@ __device__ void score_region(Lane<R> &p, const KArgs &a, const Shared &sh, const
     const R dx = p.x - (R)J.region_c[0], dy = p.y - (R)J.region_c[1];
     const R rr = (R)J.region_r;
     const R A = wx * wx + wy * wy, B = dx * wx + dy * wy, Cc = dx * dx + dy * dy - rr * rr;
-    if (A == (R)0) {
-        if (!(Cc < (R)0)) return;
-    } else {
-        const R disc = B * B - A * Cc;
-        if (!(disc > (R)0)) return;
-        const R sq = Pr<R>::sq(disc);
-        const R ta = (-B - sq) / A, tb = (-B + sq) / A;
-        if (ta > lo) lo = ta;
-        if (tb < hi) hi = tb;
+    bool within = false;
+    if constexpr (sizeof(R) == 4) {
+        // production: a segment whose two ends are inside the cylinder lies in
+        // it (the disc is convex), the usual case for a wide probe
+        const R ex = dx + wx * seg, ey = dy + wy * seg;
+        within = (Cc < (R)0) && (ex * ex + ey * ey < rr * rr);
+    }
+    if (!within) {
+        if (A == (R)0) {
+            if (!(Cc < (R)0)) return;
+        } else {
+            const R disc = B * B - A * Cc;
+            if (!(disc > (R)0)) return;
+            const R sq = Pr<R>::sq(disc);
+            const R ta = (-B - sq) / A, tb = (-B + sq) / A;
+            if (ta > lo) lo = ta;
+            if (tb < hi) hi = tb;
+        }
     }
     if (!(hi > lo)) return;
     const double t0 = p.t + (double)lo, t1 = p.t + (double)hi;
+    if (p.rwin >= 0 && t1 <= p.rwend && t0 >= p.rwbeg) {  // inside the window being summed
+        p.rt += (double)p.s * (t1 - t0);
+        p.rq += (double)p.s * (double)p.v * (double)p.oz * (t1 - t0);
+        return;
+    }
     const double *times = a.times + J.times_off;
     int j = (p.rwin > 0) ? p.rwin : 0;
     double w0 = (j == 0) ? 0.0 : times[j - 1];
@@ -701,6 +737,8 @@ __device__ void score_region(Lane<R> &p, const KArgs &a, const Shared &sh, const
             if (j != p.rwin) {
                 region_flush(p, a, sh, J);
                 p.rwin = j;
+                p.rwbeg = w0;
+                p.rwend = w1;
             }
             p.rt += (double)p.s * (h - l);
             p.rq += (double)p.s * (double)p.v * (double)p.oz * (h - l);
@@ -900,6 +938,10 @@ __device__ void resume(Lane<R> &p, const KArgs &a, const Shared &sh, uint32_t i)
     p.rt = S.rt;
     p.rq = S.rq;
     p.rwin = S.rwin;
+    if (p.rwin >= 0) {
+        p.rwbeg = (p.rwin == 0) ? 0.0 : a.times[J.times_off + p.rwin - 1];
+        p.rwend = a.times[J.times_off + p.rwin];
+    }
     load_state(p, a, sh, S.m);
     set_kbin(p);
     p.cbin = (p.n_bins > 0) ? p.kbin : -1;
@@ -966,7 +1008,7 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
 {
     const uint4 w = philox_step(p);
     ++p.k;
-    const R dt = Pr<R>::flight(p.tau, w.x);                           // step II
+    const R dt = Pr<R>::flight(sizeof(R) == 4 ? p.ntl : p.tau, w.x);  // step II
     int32_t surf;
     const int geom = (G == GEOM_ANY || G == GEOM_GRAD) ? p.geom : G;
     const R tb = search(p, J, geom, surf);                           // step III
