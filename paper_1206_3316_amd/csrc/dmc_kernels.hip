@@ -210,6 +210,8 @@ struct Lane {
     double tnext, tend;  // next snapshot time and final time (+inf when steady)
     // windowed region tally: top of the region (-inf without one), the window
     // whose sums the particle is accumulating (-1: none) and those sums
+    int32_t pend;           // deferred snapshot crossing: time index (-1: none) and position
+    R px, py, pz;
     R rzhi;
     int32_t rwin;
     double rt, rq;
@@ -335,6 +337,7 @@ __device__ __forceinline__ void bind_job(Lane<R> &p, const JobDev &J, uint64_t p
     p.rzhi = (J.off_region >= 0 && (G == GEOM_HALF || G == GEOM_ANY)) ? (R)J.region_z[1] : -Pr<R>::inf();
     p.rwin = -1;
     p.rt = p.rq = 0.0;
+    p.pend = -1;
     {
         const int32_t boff = p.batch * 3 * p.n_bins;
         p.bl = (J.lds_bins >= 0) ? J.lds_bins + boff : -1;
@@ -452,6 +455,13 @@ __device__ __forceinline__ void bins_add(const Lane<R> &p, const KArgs &a, const
         atomicAdd(sh.ltally + (p.bl + idx), v);
     else
         tadd(a, sh, p.bl, p.bg, idx, v);
+}
+
+// Deferred snapshot scoring: FP32 persistent half-space kernel.
+template <typename R, int FORM, int G>
+__device__ constexpr bool defer_snapshots()
+{
+    return sizeof(R) == 4 && FORM == FORM_PERSISTENT && G == GEOM_HALF;
 }
 
 // Telescoped displacement (persistent slab kernel): the signed length a particle
@@ -613,52 +623,86 @@ __device__ void score_bins(Lane<R> &p, const KArgs &a, const Shared &sh, const J
     }
 }
 
-// Snapshot estimator (Eq. (3)) at every sample time in [t, t + seg).
+// Adds s to snapshot tally time_index at the cell that holds position (x, y, z).
 template <typename R>
+__device__ __forceinline__ void snapshot_add(const Lane<R> &p, const KArgs &a, const JobDev &J, int32_t ti, R x, R y,
+                                             R z, double dt)
+{
+    int64_t idx[3];
+    bool inside = true;
+    if constexpr (sizeof(R) == 4) {
+        // production: the cell in FP32 with a precomputed scale (no divisions)
+        const float pos[3] = {x, y, z};
+        for (int d = 0; d < 3; ++d) {
+            const float fl = floorf((pos[d] - J.grid_lof[d]) * J.grid_scf[d]);
+            if (!(fl >= 0.0f && fl < (float)J.grid[d])) {
+                inside = false;
+                break;
+            }
+            idx[d] = (int64_t)fl;
+        }
+    } else {
+        // parity: the FP64 reference's operations
+        const double pos[3] = {(double)p.x + (double)(p.v * p.ox) * dt, (double)p.y + (double)(p.v * p.oy) * dt,
+                               (double)p.z + (double)(p.v * p.oz) * dt};
+        for (int d = 0; d < 3; ++d) {
+            const double f = (pos[d] - J.grid_lo[d]) / J.grid_ext[d] * (double)J.grid[d];
+            const double fl = floor(f);
+            if (!(fl >= 0.0 && fl < (double)J.grid[d])) {
+                inside = false;
+                break;
+            }
+            idx[d] = (int64_t)fl;
+        }
+    }
+    const int64_t cell = inside ? (idx[2] * J.grid[1] + idx[1]) * J.grid[0] + idx[0] : J.ncell;
+    const int64_t o = (int64_t)ti * (J.ncell + 1) + cell;
+    gadd(a.tally + J.off_snap + o, (double)p.s);
+    if (J.snap_abs_on) gadd(a.tally + J.off_snap_abs + o, 1.0);
+}
+
+// Scores the particle's recorded snapshot crossing, if any.
+template <typename R>
+__device__ __forceinline__ void snapshot_commit(Lane<R> &p, const KArgs &a, const JobDev &J)
+{
+    if (p.pend < 0) return;
+    snapshot_add(p, a, J, p.pend, p.px, p.py, p.pz, 0.0);
+    p.pend = -1;
+}
+
+// Snapshot estimator (Eq. (3)) at every sample time in [t, t + seg): the
+// particle's position there, by linear interpolation along the segment,
+// selects the grid cell (or the overflow slot) that receives s.  With DEFER
+// (production half-space kernel) a crossing is recorded in registers and scored
+// later together with other lanes' (snapshot_commit), so that the divergent
+// cell and atomic work runs once for many lanes.
+template <typename R, bool DEFER>
 __device__ void score_snapshots(Lane<R> &p, const KArgs &a, const JobDev &J, double seg)
 {
     const double ta = p.t, tb = p.t + seg;
     const double *times = a.times + J.times_off;
-    while (p.tcur < p.n_times && times[p.tcur] < tb) {
-        const double tj = times[p.tcur];
+    while (p.tnext < tb) {
+        const double tj = p.tnext;
         if (tj >= ta) {
             const double dt = tj - ta;
-            int64_t idx[3];
-            bool inside = true;
-            if constexpr (sizeof(R) == 4) {
-                // production: the cell in FP32 with a precomputed scale (no divisions)
-                const float dtf = (float)dt;
-                const float pos[3] = {p.x + (p.v * p.ox) * dtf, p.y + (p.v * p.oy) * dtf, p.z + (p.v * p.oz) * dtf};
-                for (int d = 0; d < 3; ++d) {
-                    const float fl = floorf((pos[d] - J.grid_lof[d]) * J.grid_scf[d]);
-                    if (!(fl >= 0.0f && fl < (float)J.grid[d])) {
-                        inside = false;
-                        break;
-                    }
-                    idx[d] = (int64_t)fl;
-                }
+            if constexpr (DEFER) {
+                snapshot_commit(p, a, J);  // a second crossing before the last was scored
+                const R dtf = (R)dt;
+                p.pend = p.tcur;
+                p.px = p.x + (p.v * p.ox) * dtf;
+                p.py = p.y + (p.v * p.oy) * dtf;
+                p.pz = p.z + (p.v * p.oz) * dtf;
+            } else if constexpr (sizeof(R) == 4) {
+                const R dtf = (R)dt;
+                snapshot_add(p, a, J, p.tcur, p.x + (p.v * p.ox) * dtf, p.y + (p.v * p.oy) * dtf,
+                             p.z + (p.v * p.oz) * dtf, dt);
             } else {
-                // parity: the FP64 reference's operations
-                const double pos[3] = {(double)p.x + (double)(p.v * p.ox) * dt, (double)p.y + (double)(p.v * p.oy) * dt,
-                                       (double)p.z + (double)(p.v * p.oz) * dt};
-                for (int d = 0; d < 3; ++d) {
-                    const double f = (pos[d] - J.grid_lo[d]) / J.grid_ext[d] * (double)J.grid[d];
-                    const double fl = floor(f);
-                    if (!(fl >= 0.0 && fl < (double)J.grid[d])) {
-                        inside = false;
-                        break;
-                    }
-                    idx[d] = (int64_t)fl;
-                }
+                snapshot_add(p, a, J, p.tcur, p.x, p.y, p.z, dt);
             }
-            const int64_t cell = inside ? (idx[2] * J.grid[1] + idx[1]) * J.grid[0] + idx[0] : J.ncell;
-            const int64_t o = (int64_t)p.tcur * (J.ncell + 1) + cell;
-            gadd(a.tally + J.off_snap + o, (double)p.s);
-            if (J.snap_abs_on) gadd(a.tally + J.off_snap_abs + o, 1.0);
         }
         ++p.tcur;
+        p.tnext = (p.tcur < p.n_times) ? times[p.tcur] : __builtin_huge_val();
     }
-    p.tnext = (p.tcur < p.n_times) ? times[p.tcur] : __builtin_huge_val();
 }
 
 // Adds the particle's sums of its current region window to the tallies.
@@ -954,6 +998,7 @@ __device__ void finish(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDe
 {
     if (p.n_bins > 0) bin_flush<R, FORM, G>(p, a, sh);
     if (G == GEOM_HALF || G == GEOM_ANY) region_flush(p, a, sh, J);
+    if (defer_snapshots<R, FORM, G>()) snapshot_commit(p, a, J);
     if (telescoped<FORM, G>() && p.n_bins > 0) {
         // end term of the telescoped displacement: F_k(z_end) for every bin
         const R z = p.z;
@@ -1024,7 +1069,7 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
     }
     if (G == GEOM_ANY || G == GEOM_HALF) {
         const double tb_abs = p.t + (double)seg;
-        if (p.tnext < tb_abs) score_snapshots(p, a, J, (double)seg);
+        if (p.tnext < tb_abs) score_snapshots<R, defer_snapshots<R, FORM, G>()>(p, a, J, (double)seg);
         // windowed region tally; most segments lie wholly above the region
         if (fmin(p.z, p.z + p.v * p.oz * seg) < p.rzhi) score_region(p, a, sh, J, seg);
         if (tb_abs > p.tend) return 1;  // step VI
@@ -1304,6 +1349,11 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                 finish<R, FORM_PERSISTENT, G>(p, a, sh, J, r == 2);
                 alive = false;
             }
+        }
+        if (defer_snapshots<R, FORM_PERSISTENT, G>()) {
+            // score the recorded crossings together once a quarter of the wave has one
+            if (__popcll(__ballot(alive && p.pend >= 0)) >= 16 && alive && p.pend >= 0)
+                snapshot_commit(p, a, a.jobs[p.job]);
         }
     }
     flush_shared(a, sh);
