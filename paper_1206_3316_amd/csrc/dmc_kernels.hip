@@ -1249,6 +1249,10 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
     const int lane = (int)(threadIdx.x & 63);
     Lane<R> p;
     bool alive = false;
+    // a particle that ended keeps its registers until the lane is refilled, so
+    // that its closing tally work runs together with other lanes' (0: none, 1:
+    // ended, 2: stopped at the flight cap)
+    int ended = 0;
     int job = 0;
     uint64_t pool_cur = 0, pool_end = 0;  // wave-uniform slice of the queue
     bool qdry = false;  // the global queue has handed out every index (wave-uniform)
@@ -1260,6 +1264,10 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
         const int n_free = __popcll(need);
         const bool have_work = (pool_cur < pool_end) || !qdry;
         if (n_free > 0 && have_work && (n_free >= a.refill_min || n_free == 64)) {
+            if (ended) {
+                finish<R, FORM_PERSISTENT, G>(p, a, sh, a.jobs[p.job], ended == 2);
+                ended = 0;
+            }
             while (need) {
                 if (pool_cur >= pool_end) {
                     if (qdry) break;
@@ -1306,6 +1314,10 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
             // this wave hands its live particles, and any indices of its chunk not yet
             // started, to the next launch
             if (++drain > a.drain_iters) {
+                if (ended) {
+                    finish<R, FORM_PERSISTENT, G>(p, a, sh, a.jobs[p.job], ended == 2);
+                    ended = 0;
+                }
                 if (alive) suspend<R, FORM_PERSISTENT, G>(p, a, sh);
                 alive = false;
                 while (pool_cur < pool_end) {
@@ -1346,7 +1358,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
             const JobDev &J = a.jobs[p.job];
             const int r = step<R, FORM_PERSISTENT, G>(p, a, sh, J);
             if (r != 0) {
-                finish<R, FORM_PERSISTENT, G>(p, a, sh, J, r == 2);
+                ended = r;
                 alive = false;
             }
         }
@@ -1356,6 +1368,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                 snapshot_commit(p, a, a.jobs[p.job]);
         }
     }
+    if (ended) finish<R, FORM_PERSISTENT, G>(p, a, sh, a.jobs[p.job], ended == 2);
     flush_shared(a, sh);
 }
 
