@@ -572,6 +572,30 @@ double flights_per_particle(const dmc_material &M, const JobHost &h)
     return d.kmax >= 0 ? 1.5 * d.kmax + 1.0 : 1000.0;
 }
 
+// Flights of the longest trajectory a gradient job is likely to hold, when one
+// free path sets it: the source emits states with weight C v, and a free path
+// of mean length Lambda crosses a film or pore cell of size l about Lambda / l
+// times, each crossing or wall hit being one flight.  Among N particles the
+// longest free path is drawn from about the states whose emission weight above
+// it is 1/N.  Jobs with such a tail go first, so that it runs beside the bulk
+// of the launch rather than after it.
+double longest_flights(const dmc_material &M, const JobHost &h)
+{
+    const JobDev &d = h.dev;
+    const double cell = h.geom.length;
+    if (d.src != SRC_GRADIENT || !(cell > 0.0) || d.n == 0) return 0.0;
+    std::vector<std::pair<double, double>> lw(M.K);
+    for (int m = 0; m < M.K; ++m) lw[m] = {M.v[m] * M.tau[m], M.C[m] * M.v[m]};
+    std::sort(lw.begin(), lw.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+    const double target = M.G_v / (double)d.n;
+    double cum = 0.0;
+    for (const auto &e : lw) {
+        cum += e.second;
+        if (cum >= target) return e.first / cell;
+    }
+    return 0.0;
+}
+
 dmc_status gather_jobs(const dmc_job *jobs, int32_t n_jobs, std::vector<JobHost> &jh)
 {
     if (!jobs || n_jobs < 1 || n_jobs > kMaxJobs) return fail(DMC_E_INVALID, "n_jobs must be 1..4096");
@@ -582,11 +606,13 @@ dmc_status gather_jobs(const dmc_job *jobs, int32_t n_jobs, std::vector<JobHost>
         dmc_status st = prepare_job(jobs[i], jh[i]);
         if (st != DMC_OK) return st;
     }
-    // queue order: descending expected flights per particle (ties: caller's order)
+    // queue order: descending expected flights per particle, or the flights of a
+    // gradient job's longest likely trajectory where that is larger (ties:
+    // caller's order)
     std::vector<int> order(n_jobs);
     for (int i = 0; i < n_jobs; ++i) order[i] = i;
     std::vector<double> f(n_jobs);
-    for (int i = 0; i < n_jobs; ++i) f[i] = flights_per_particle(*M, jh[i]);
+    for (int i = 0; i < n_jobs; ++i) f[i] = std::max(flights_per_particle(*M, jh[i]), longest_flights(*M, jh[i]));
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return f[x] > f[y]; });
     uint64_t base = 0;
     for (int r = 0; r < n_jobs; ++r) {

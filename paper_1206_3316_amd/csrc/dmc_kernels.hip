@@ -1251,7 +1251,9 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
     bool alive = false;
     // a particle that ended keeps its registers until the lane is refilled, so
     // that its closing tally work runs together with other lanes' (0: none, 1:
-    // ended, 2: stopped at the flight cap)
+    // ended, 2: stopped at the flight cap). Not in time-bounded launches: there
+    // the longer live ranges push the generic kernel past 128 VGPRs into spills.
+    constexpr bool DEFER_FINISH = !BOUNDED;
     int ended = 0;
     int job = 0;
     uint64_t pool_cur = 0, pool_end = 0;  // wave-uniform slice of the queue
@@ -1358,7 +1360,10 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
             const JobDev &J = a.jobs[p.job];
             const int r = step<R, FORM_PERSISTENT, G>(p, a, sh, J);
             if (r != 0) {
-                ended = r;
+                if (DEFER_FINISH)
+                    ended = r;
+                else
+                    finish<R, FORM_PERSISTENT, G>(p, a, sh, J, r == 2);
                 alive = false;
             }
         }
