@@ -1033,25 +1033,55 @@ __device__ void finish(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDe
 
 // ------------------------------------------------------------------ step ----
 
-// The STEP block of flight k.  When every active lane of the wave carries the
-// same key (the usual case: a wave's particles come from one job), the key
-// schedule runs once on the scalar unit instead of once per lane.
+// Key of a wave's particles when they all carry the same one (the usual case:
+// a wave's particles come from one job): the Philox key schedule of the STEP
+// block then runs once on the scalar unit instead of once per lane.
+struct WaveKey {
+    uint32_t k0, k1;
+    bool uniform;
+};
+
+// Over the live lanes; particles change only where lanes are refilled, so the
+// persistent loop refreshes it there.
 template <typename R>
-__device__ __forceinline__ uint4 philox_step(const Lane<R> &p)
+__device__ __forceinline__ WaveKey wave_key(const Lane<R> &p, bool alive)
+{
+    WaveKey w{0u, 0u, false};
+    const uint64_t live = __ballot(alive);
+    if (live == 0ull) return w;
+    const int src = __ffsll((unsigned long long)live) - 1;
+    w.k0 = __builtin_amdgcn_readlane(p.key0, src);
+    w.k1 = __builtin_amdgcn_readlane(p.key1, src);
+    w.uniform = __ballot(alive && (p.key0 != w.k0 || p.key1 != w.k1)) == 0ull;
+    return w;
+}
+
+// Over the active lanes (plain form).
+template <typename R>
+__device__ __forceinline__ WaveKey wave_key_active(const Lane<R> &p)
+{
+    WaveKey w;
+    w.k0 = __builtin_amdgcn_readfirstlane(p.key0);
+    w.k1 = __builtin_amdgcn_readfirstlane(p.key1);
+    w.uniform = __ballot(p.key0 != w.k0 || p.key1 != w.k1) == 0ull;
+    return w;
+}
+
+// The STEP block of flight k.
+template <typename R>
+__device__ __forceinline__ uint4 philox_step(const Lane<R> &p, const WaveKey &wk)
 {
     const uint32_t c0 = (uint32_t)p.pid, c1 = (uint32_t)(p.pid >> 32);
-    const uint32_t k0 = __builtin_amdgcn_readfirstlane(p.key0);
-    const uint32_t k1 = __builtin_amdgcn_readfirstlane(p.key1);
-    if (__ballot(p.key0 != k0 || p.key1 != k1) == 0ull) return philox(c0, c1, p.k, TAG_STEP, k0, k1);
+    if (wk.uniform) return philox(c0, c1, p.k, TAG_STEP, wk.k0, wk.k1);
     return philox(c0, c1, p.k, TAG_STEP, p.key0, p.key1);
 }
 
 // One iteration of steps II-VI.  Returns 0 if the particle goes on, 1 if it
 // ended, 2 if it hit the flight cap.
 template <typename R, int FORM, int G>
-__device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J)
+__device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, const WaveKey &wk)
 {
-    const uint4 w = philox_step(p);
+    const uint4 w = philox_step(p, wk);
     ++p.k;
     const R dt = Pr<R>::flight(sizeof(R) == 4 ? p.ntl : p.tau, w.x);  // step II
     int32_t surf;
@@ -1225,17 +1255,19 @@ __global__ void __launch_bounds__(256) plain_kernel(KArgs a)
         emit<R, G>(p, a, sh, J, q, job);
         int r;
         do {
-            r = step<R, FORM_PLAIN, G>(p, a, sh, J);
+            r = step<R, FORM_PLAIN, G>(p, a, sh, J, wave_key_active(p));
         } while (r == 0);
         finish<R, FORM_PLAIN, G>(p, a, sh, J, r == 2);
     }
     flush_shared(a, sh);
 }
 
-__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int src)
 {
-    const uint32_t lo = __shfl((uint32_t)v, src, 64);
-    const uint32_t hi = __shfl((uint32_t)(v >> 32), src, 64);
+    // src is wave-uniform, so the value lands in scalar registers: the queue
+    // state derived from it stays scalar and the loop's control stays uniform
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, src);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), src);
     return ((uint64_t)hi << 32) | lo;
 }
 
@@ -1259,6 +1291,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
     uint64_t pool_cur = 0, pool_end = 0;  // wave-uniform slice of the queue
     bool qdry = false;  // the global queue has handed out every index (wave-uniform)
     uint32_t drain = 0, poll = 0, iter = 0;
+    WaveKey wk{0u, 0u, false};
     for (;;) {
         // refill free lanes from this wave's chunk, taking a new chunk from the
         // queue (one atomic per wave) when it is used up
@@ -1276,7 +1309,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                     const int leader = __ffsll((unsigned long long)need) - 1;
                     uint64_t b = 0;
                     if (lane == leader) b = atomicAdd(a.queue, (unsigned long long)a.chunk);
-                    b = shfl64(b, leader);
+                    b = readlane64(b, leader);
                     if (b >= a.total) {
                         qdry = true;
                         break;
@@ -1304,6 +1337,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                 pool_cur += (uint64_t)take;
                 need &= ~__ballot(mine);
             }
+            wk = wave_key(p, alive);
         }
         if (BOUNDED && !qdry && ((++poll) & 63u) == 0u) {
             // waves whose lanes are all busy also learn when the queue ran dry
@@ -1358,7 +1392,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
         }
         if (alive) {
             const JobDev &J = a.jobs[p.job];
-            const int r = step<R, FORM_PERSISTENT, G>(p, a, sh, J);
+            const int r = step<R, FORM_PERSISTENT, G>(p, a, sh, J, wk);
             if (r != 0) {
                 if (DEFER_FINISH)
                     ended = r;
