@@ -268,8 +268,10 @@ __device__ __forceinline__ void tadd(const KArgs &a, const Shared &sh, int32_t l
 template <typename R>
 __device__ __forceinline__ int bin_of(R c, R bpl, int nb)
 {
-    int k = (int)floor(c * bpl);
-    return k < 0 ? 0 : (k > nb - 1 ? nb - 1 : k);
+    // truncation instead of floor: a product in (-1, 0) gives 0, which is the
+    // clamped bin either way
+    const int k = (int)(c * bpl);
+    return min(max(k, 0), nb - 1);
 }
 
 template <typename R>
@@ -576,13 +578,15 @@ __device__ void score_bins(Lane<R> &p, const KArgs &a, const Shared &sh, const J
         const int kb = bin_of(cb, p.bpl, nb);
         p.kbin = kb;
         if (ka == kb) return;
-        const R inv = Pr<R>::div((R)1, fabs(wa));
+        // time past the edge the particle crossed last: (cb - edge) / wa, one
+        // expression for both directions (the same value as |cb - edge| / |wa|)
+        const R inv = Pr<R>::div((R)1, wa);
         const R bw = p.bw;
         const bool up = wa > (R)0;
-        const R t1 = up ? fmax((cb - (R)kb * bw) * inv, (R)0) : fmax(((R)(kb + 1) * bw - cb) * inv, (R)0);
+        const R t1 = fmax((cb - (R)(up ? kb : kb + 1) * bw) * inv, (R)0);
         const int nin = (up ? kb - ka : ka - kb) - 1;  // bins crossed from edge to edge
         if (nin > 0) {
-            const R tin = bw * inv;
+            const R tin = bw * fabs(inv);
             const int step = up ? 1 : -1;
             for (int k = ka + step; k != kb; k += step) bin_add<R, FORM, G>(p, a, sh, k, tin, vz, false);
             bin_add<R, FORM, G>(p, a, sh, ka, -((R)nin * tin), vz, true);
@@ -1288,7 +1292,10 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
     constexpr bool DEFER_FINISH = !BOUNDED;
     int ended = 0;
     int job = 0;
-    uint64_t pool_cur = 0, pool_end = 0;  // wave-uniform slice of the queue
+    // wave-uniform slice of the queue: next index and how many are left (a chunk
+    // fits 32 bits, so the tests below are scalar compares)
+    uint64_t pool_cur = 0;
+    uint32_t pool_left = 0;
     bool qdry = false;  // the global queue has handed out every index (wave-uniform)
     uint32_t drain = 0, poll = 0, iter = 0;
     WaveKey wk{0u, 0u, false};
@@ -1297,14 +1304,14 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
         // queue (one atomic per wave) when it is used up
         uint64_t need = __ballot(!alive);
         const int n_free = __popcll(need);
-        const bool have_work = (pool_cur < pool_end) || !qdry;
+        const bool have_work = pool_left > 0u || !qdry;
         if (n_free > 0 && have_work && (n_free >= a.refill_min || n_free == 64)) {
             if (ended) {
                 finish<R, FORM_PERSISTENT, G>(p, a, sh, a.jobs[p.job], ended == 2);
                 ended = 0;
             }
             while (need) {
-                if (pool_cur >= pool_end) {
+                if (pool_left == 0u) {
                     if (qdry) break;
                     const int leader = __ffsll((unsigned long long)need) - 1;
                     uint64_t b = 0;
@@ -1315,9 +1322,9 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                         break;
                     }
                     pool_cur = b;
-                    pool_end = (b + (uint64_t)a.chunk < a.total) ? b + (uint64_t)a.chunk : a.total;
+                    pool_left = (b + (uint64_t)a.chunk < a.total) ? (uint32_t)a.chunk : (uint32_t)(a.total - b);
                 }
-                const uint64_t avail = pool_end - pool_cur;
+                const uint32_t avail = pool_left;
                 const int cnt = __popcll(need);
                 const int take = ((uint64_t)cnt < avail) ? cnt : (int)avail;
                 const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
@@ -1335,6 +1342,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                     alive = true;
                 }
                 pool_cur += (uint64_t)take;
+                pool_left -= (uint32_t)take;
                 need &= ~__ballot(mine);
             }
             wk = wave_key(p, alive);
@@ -1344,7 +1352,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
             const unsigned long long head = __hip_atomic_load(a.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (head >= a.total) qdry = true;
         }
-        if (__ballot(alive) == 0ull && !((pool_cur < pool_end) || !qdry)) break;
+        if (__ballot(alive) == 0ull && !(pool_left > 0u || !qdry)) break;
         if (BOUNDED && qdry) {
             // time-bounded launch: the queue is dry; a fixed number of flights later
             // this wave hands its live particles, and any indices of its chunk not yet
@@ -1356,8 +1364,8 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                 }
                 if (alive) suspend<R, FORM_PERSISTENT, G>(p, a, sh);
                 alive = false;
-                while (pool_cur < pool_end) {
-                    const uint64_t avail = pool_end - pool_cur;
+                while (pool_left > 0u) {
+                    const uint32_t avail = pool_left;
                     const bool mine = (uint64_t)lane < avail;
                     if (mine) {
                         const uint64_t q = pool_cur + (uint64_t)lane;
@@ -1369,7 +1377,9 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                         }
                         suspend<R, FORM_PERSISTENT, G>(p, a, sh);
                     }
-                    pool_cur += (avail < 64u) ? avail : 64u;
+                    const uint32_t n = (avail < 64u) ? avail : 64u;
+                    pool_cur += n;
+                    pool_left -= n;
                 }
                 break;
             }
