@@ -298,9 +298,9 @@ def main():
                          "profiles use it so that only the timed launches are traced")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=500)
     ap.add_argument("--epoch-flights", type=float, default=2e10)
-    ap.add_argument("--serve-max-s", type=float, default=90.0, help="stop admitting requests after this long")
+    ap.add_argument("--serve-max-s", type=float, default=120.0, help="stop admitting requests after this long")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the single-launch measurements of the heated spot and the batched nanostructures")

@@ -736,7 +736,7 @@ __device__ void score_region(Lane<R> &p, const KArgs &a, const Shared &sh, const
     if (wz == (R)0) {
         if (!(p.z >= (R)J.region_z[0] && p.z < (R)J.region_z[1])) return;
     } else {
-        R ta = ((R)J.region_z[0] - p.z) / wz, tb = ((R)J.region_z[1] - p.z) / wz;
+        R ta = Pr<R>::div((R)J.region_z[0] - p.z, wz), tb = Pr<R>::div((R)J.region_z[1] - p.z, wz);
         if (ta > tb) {
             const R s = ta;
             ta = tb;
@@ -763,7 +763,7 @@ __device__ void score_region(Lane<R> &p, const KArgs &a, const Shared &sh, const
             const R disc = B * B - A * Cc;
             if (!(disc > (R)0)) return;
             const R sq = Pr<R>::sq(disc);
-            const R ta = (-B - sq) / A, tb = (-B + sq) / A;
+            const R ta = Pr<R>::div(-B - sq, A), tb = Pr<R>::div(-B + sq, A);
             if (ta > lo) lo = ta;
             if (tb < hi) hi = tb;
         }
@@ -882,7 +882,7 @@ __device__ bool interact(Lane<R> &p, const JobDev &J, int32_t surf, const uint4 
         const R c = (R)0.5 * p.len;
         const R nx = p.x - c, nz = p.z - c;
         const R nn = Pr<R>::sq(nx * nx + nz * nz);
-        const R n0 = nx / nn, n2 = nz / nn;
+        const R n0 = Pr<R>::div(nx, nn), n2 = Pr<R>::div(nz, nn);
         if ((uint64_t)w.y < J.spec_thr[0]) {
             const R dn = p.ox * n0 + p.oz * n2;
             p.ox = p.ox - (R)2 * dn * n0;
