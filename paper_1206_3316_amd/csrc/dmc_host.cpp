@@ -372,7 +372,7 @@ int kernel_spec(const JobDev *jobs, int n_jobs)
     for (int i = 0; i < n_jobs; ++i) {
         const JobDev &d = jobs[i];
         if (d.geom != GEOM_SLAB || d.src != SRC_WALLS || d.n_times > 0 || d.wall_type[0] == WALL_PERIODIC ||
-            d.wall_type[1] == WALL_PERIODIC || d.kmax >= 0)
+            d.wall_type[1] == WALL_PERIODIC || d.kmax >= 0 || d.n_bins <= 0)
             slab = false;
         if (d.geom != GEOM_HALF || d.src != SRC_GAUSSIAN || d.n_times == 0 || d.n_bins > 0 || d.off_kappa >= 0 ||
             d.n_hj > 0)

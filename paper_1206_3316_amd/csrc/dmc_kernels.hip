@@ -571,9 +571,9 @@ __device__ void score_bins(Lane<R> &p, const KArgs &a, const Shared &sh, const J
     const int ka = p.kbin;  // bin_of(ca): the end bin of the previous segment
     if constexpr (FORM == FORM_PERSISTENT) {
         bin_add<R, FORM, G>(p, a, sh, ka, seg, vz, true);
-        if (wa == (R)0) return;
         // the position update of the step computes exactly cb, so kb is the next
-        // segment's start bin (a boundary interaction recomputes it)
+        // segment's start bin (a boundary interaction recomputes it); a flight
+        // parallel to the bins stays in bin ka
         const R cb = ca + wa * seg;
         const int kb = bin_of(cb, p.bpl, nb);
         p.kbin = kb;
@@ -1094,7 +1094,7 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
     const bool boundary = (tb <= dt);
     const R seg = boundary ? tb : dt;
     // step V: sample the segment
-    if (p.n_bins > 0) score_bins<R, FORM, G>(p, a, sh, J, seg);
+    if (G == GEOM_SLAB || p.n_bins > 0) score_bins<R, FORM, G>(p, a, sh, J, seg);  // the slab kernel always has bins
     const bool gradient = (G == GEOM_GRAD) || ((G == GEOM_ANY) && (p.src == SRC_GRADIENT));
     if (gradient) {
         const double dz = (double)(p.s * p.v * p.oz * seg);
@@ -1127,7 +1127,7 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
         }
         ++p.nbound;
         if (interact(p, J, surf, w)) return 1;
-        if (p.n_bins > 0) {
+        if (G == GEOM_SLAB || p.n_bins > 0) {
             set_kbin(p);  // a periodic face moves the particle to the other end
             if (FORM == FORM_PERSISTENT) bin_enter<R, FORM, G>(p, a, sh, p.kbin);
         }

@@ -171,10 +171,10 @@ extern "C" dmc_status dmc_autotune(const dmc_job *jobs, int32_t n_jobs, const dm
         ++t.n_trials;
     };
 
-    Choice cur;  // the planner's defaults (block 0: sized from the LDS the batch needs)
+    Choice cur;  // start: block 0 (sized from the LDS the batch needs), chunk 1024, refill at 4 free lanes
     cur.block = 0;
     cur.chunk = 1024;
-    cur.refill_min = 16;
+    cur.refill_min = 4;
     cur.lds_tally = o.lds_tally;
     double cur_ms = 0.0;
     // the first launch loads the code object and sets LDS attributes: not timed
