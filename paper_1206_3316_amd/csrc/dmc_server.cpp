@@ -106,7 +106,11 @@ struct dmc_server {
     uint32_t susp_cap = 0;
     int cur = 0;                     // buffer holding the previous epoch's suspended particles
     uint32_t n_susp = 0;
+    // last epoch's members and how many particles each left suspended; a member
+    // with none may have finished and been collected since, so its pointer is
+    // never followed
     std::vector<Request *> prev_members;
+    std::vector<uint64_t> prev_suspended;
     int32_t *d_resume_job = nullptr;
     std::vector<int32_t> h_resume_job;
     dmc_stats totals{};              // all epochs so far
@@ -266,12 +270,12 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
         // epoch's job table (jobs are queued in member order, so index = member)
         S->h_resume_job.assign((size_t)S->opts.max_active, 0);
         for (size_t i = 0; i < S->prev_members.size(); ++i) {
+            if (S->prev_suspended[i] == 0) continue;  // no particle of this slot resumes
             int32_t idx = -1;
             for (size_t j = 0; j < members.size(); ++j)
                 if (members[j] == S->prev_members[i]) idx = (int32_t)j;
-            if (idx < 0 && S->prev_members[i]->suspended)
-                return fail(DMC_E_DEVICE, "internal: a request with suspended particles left the epoch");
-            S->h_resume_job[i] = idx < 0 ? 0 : idx;
+            if (idx < 0) return fail(DMC_E_DEVICE, "internal: a request with suspended particles left the epoch");
+            S->h_resume_job[i] = idx;
         }
     }
     DMC_HIP_OR_FAIL(hipMemcpyAsync(S->d_resume_job, S->h_resume_job.data(), S->h_resume_job.size() * sizeof(int32_t),
@@ -316,6 +320,8 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
     S->totals.kernel_ms += ms;
     S->cur = 1 - S->cur;
     S->prev_members = members;
+    S->prev_suspended.resize(members.size());
+    for (size_t i = 0; i < members.size(); ++i) S->prev_suspended[i] = members[i]->suspended;
     for (size_t i = 0; i < S->active.size();) {
         Request *r = S->active[i].get();
         if (r->cursor >= r->jh.dev.n && r->suspended == 0) {

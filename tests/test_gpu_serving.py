@@ -99,3 +99,32 @@ def test_suspend_resume_is_exact_against_oracle():
         st = res.stats(0)
         assert st.particles == job.n_particles and st.scatters == ocnt["scatters"], job.name
     srv.close()
+
+
+def test_results_collected_between_epochs():
+    """Each request is collected (and its result freed) in the step where it
+    completes, while the others keep running with suspended particles: the
+    server must not consult a collected request when it maps the particles that
+    resume in the next epoch."""
+    si = di.silicon_like()
+    mat = b.Material(si)
+    reqs = _requests(si) + [di.slab_job(si, 5e-7, 40_000, seed=2007, n_bins=20),
+                            small_spot(n=12_000, seed=2008, grid=8, n_times=5, mat=si)]
+    srv = b.Server(mat, memory_budget=8 << 20, max_active=4, epoch_flights=2e6, drain_flights=64)
+    tickets = {srv.submit(j): j for j in reqs}
+    left = dict(tickets)
+    steps = 0
+    while left:
+        srv.step()
+        steps += 1
+        assert steps < 10_000
+        for t in [t for t in left if srv.done(t)]:
+            job = left.pop(t)
+            res = srv.collect(t)
+            solo = b.simulate([job], material=mat)
+            assert rel_diff(res.raw(0), solo.raw(0)) <= 1e-12, job.name
+            res.close()
+            solo.close()
+    assert steps >= 4
+    assert srv.load() == (0, 0)
+    srv.close()
