@@ -302,6 +302,9 @@ def main():
     ap.add_argument("--epoch-flights", type=float, default=2e10)
     ap.add_argument("--serve-max-s", type=float, default=120.0, help="stop admitting requests after this long")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--only", choices=["spot", "nano"], default=None,
+                    help="one launch of the heated spot (1e9, 64^3 x 50) or of the 64 nanostructures, "
+                         "nothing else (for profiling those kernels)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the single-launch measurements of the heated spot and the batched nanostructures")
     args = ap.parse_args()
@@ -309,7 +312,7 @@ def main():
         copy_probe()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in DESIGN.md"}))
+        print(json.dumps({"error": "one GPU only: run with --gpus 1 (sharding particle ranges across GPUs is not implemented)"}))
         sys.exit(2)
 
     import torch
@@ -322,6 +325,17 @@ def main():
     jobs = di.cross_plane_films(n_per_film=int(args.n), material=mat_in)
     mat = b.Material(mat_in)
     stream = torch.cuda.current_stream()
+    if args.only:
+        ojobs = [di.heated_spot(material=mat_in)] if args.only == "spot" else di.batched_nanostructures(material=mat_in)
+        params = launch_params(ojobs, mat, stream=stream,
+                               overrides={"chunk": args.chunk, "refill_min": args.refill_min, "block": args.block},
+                               tune=not args.no_tune)
+        r = b.simulate(ojobs, material=mat, stream=stream, **params)
+        st = [r.stats(i) for i in range(len(ojobs))]
+        print(json.dumps({"workload": args.only, "launch": params, "kernel_ms": st[0].kernel_ms,
+                          "flights": sum(x.iterations for x in st), "scattering_events": sum(x.scatters for x in st),
+                          "particles": sum(x.particles for x in st)}))
+        return
     nbytes = b.workspace_bytes(jobs, mat)
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     t_tune = time.perf_counter()

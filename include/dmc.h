@@ -42,7 +42,7 @@ typedef int32_t dmc_status;
 #define DMC_E_INVALID (-1)     /* an argument is out of range or inconsistent */
 #define DMC_E_NOMEM (-2)       /* host or device allocation failed / workspace too small */
 #define DMC_E_DEVICE (-3)      /* a HIP call failed (no device, launch failure, ...) */
-#define DMC_E_UNSUPPORTED (-4) /* valid request this build does not implement */
+#define DMC_E_UNSUPPORTED (-4) /* valid request the library does not implement */
 #define DMC_E_BUSY (-5)        /* the server cannot admit more work right now */
 
 /* Thread-local description of the last failure on this thread ("" if none). */
