@@ -24,6 +24,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -55,7 +56,7 @@ OPS_PER_FLIGHT = 100
 # WRITE_SIZE runs (profiles/), scaled by the same counters' reading for a plain
 # device copy of known size (bench.py --copy-probe); valid only for the kernel
 # source it was measured on.
-TRAFFIC = {"kernel_sha1": "019a0be36d72ae89e21f78fb8827009e9ef939e0", "bytes": 54557886}  # profiles/persistent_kernel_slab_12films_counters.md
+TRAFFIC = {"kernel_sha1": "9f959167c05a2daa6847c24820eeeee1dc301c36", "bytes": 54557886}  # profiles/persistent_kernel_slab_12films_counters.md
 CU, LANES_PER_CU_CLK, CLOCK = 256, 64, 2.4e9
 PEAK_LANE_OPS = CU * LANES_PER_CU_CLK * CLOCK  # 3.93e13 full-rate VALU lane-ops/s
 
@@ -285,8 +286,16 @@ def copy_probe():
 
 
 def kernel_sha1():
-    p = os.path.join(ROOT, "paper_1206_3316_amd", "csrc", "dmc_kernels.hip")
-    return hashlib.sha1(open(p, "rb").read()).hexdigest()
+    """Hash of the device code with comments and layout removed (the kernel
+    source and its private header): a comment edit keeps the counters valid,
+    any code change invalidates them."""
+    h = hashlib.sha1()
+    for name in ("dmc_kernels.hip", "dmc_internal.h"):
+        src = open(os.path.join(ROOT, "paper_1206_3316_amd", "csrc", name)).read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
+    return h.hexdigest()
 
 
 def main():

@@ -206,16 +206,17 @@ struct Lane {
     int32_t kbin;           // bin that holds the current position
     double c0, c1, c2;      // entry A: the bin the particle is in
     double d0, d1, d2;      // entry B: the bin it came from
-    int32_t tcur;
-    double tnext, tend;  // next snapshot time and final time (+inf when steady)
-    // windowed region tally: top of the region (-inf without one), the window
-    // whose sums the particle is accumulating (-1: none) and those sums
+    int32_t tcur;           // index of the next snapshot time
+    double tnext, tend;     // next snapshot time and final time (+inf when steady)
     int32_t pend;           // deferred snapshot crossing: time index (-1: none) and position
     R px, py, pz;
+    // windowed region tally: top of the region (-inf without one), the window
+    // whose sums the particle is accumulating (-1: none), those sums and the
+    // window's bounds
     R rzhi;
     int32_t rwin;
     double rt, rq;
-    double rwbeg, rwend;  // bounds of window rwin
+    double rwbeg, rwend;
 };
 
 struct Shared {
