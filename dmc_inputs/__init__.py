@@ -254,13 +254,21 @@ def in_plane_film(d: float, specularity: float, n: int, seed: int, material: Opt
 
 
 def pore_cell(period: float, porosity: float, n: int, seed: int, material: Optional[Material] = None,
-              gradient: float = -1e6, kmax: int = 40, n_hj: int = 40, specularity: float = 0.0) -> Job:
-    """Square-lattice unit cell with a centred cylindrical pore of porosity pi r^2 / P^2."""
+              gradient: float = -1e6, kmax: int = 40, n_hj: int = 40, specularity: float = 0.0,
+              field: Optional[Tuple[int, int]] = None) -> Job:
+    """Square-lattice unit cell with a centred cylindrical pore of porosity pi r^2 / P^2.
+    ``field`` = (nx, nz) adds the steady temperature and z heat-flux fields on an
+    nx x nz grid over the unit cell."""
     mat = material or silicon_like()
     r = period * math.sqrt(porosity / math.pi)
     geom = Geometry("pore_cell_xz", length=period, radius=r, walls=[Wall("adiabatic", specularity=specularity)])
-    return Job(mat, geom, Source("gradient", gradient=gradient), Tally(kmax=kmax, n_hj=n_hj),
-               int(n), int(seed), f"pore_P{period:.3g}_phi{porosity}")
+    tally = Tally(kmax=kmax, n_hj=n_hj)
+    if field is not None:
+        tally.grid = (int(field[0]), 1, int(field[1]))
+        tally.grid_lo = (0.0, 0.0, 0.0)
+        tally.grid_hi = (float(period), 1.0, float(period))
+    return Job(mat, geom, Source("gradient", gradient=gradient), tally,
+               int(n), int(seed), f"pore_P{period:.3g}_phi{porosity}" + ("_field" if field else ""))
 
 
 def batched_nanostructures(n_scale: float = 1.0, seed: int = 4, material: Optional[Material] = None,

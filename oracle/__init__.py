@@ -71,6 +71,7 @@ class Problem(C.Structure):
         ("first_event", C.c_int32),
         ("region_kind", C.c_int32), ("region_c", C.c_double * 2), ("region_r", C.c_double),
         ("region_z", C.c_double * 2),
+        ("field_n", C.c_int32 * 2), ("field_lo", C.c_double * 2), ("field_hi", C.c_double * 2),
     ]
 
 
@@ -288,6 +289,15 @@ def prepare(job: di.Job) -> Prepared:
     for d in range(3):
         P.grid[d] = int(tl.grid[d]) if not steady else 0
         P.grid_lo[d], P.grid_hi[d] = float(tl.grid_lo[d]), float(tl.grid_hi[d])
+    if steady and tl.grid[0] > 0:
+        # steady pore cell: an x-z field over the unit cell (y is the cell's axis of invariance)
+        if g.kind != "pore_cell_xz" or tl.grid[1] != 1 or tl.grid[2] < 1:
+            raise ValueError("a steady field needs a pore cell and grid (nx, 1, nz)")
+        if (tl.grid_lo[0], tl.grid_lo[2], tl.grid_hi[0], tl.grid_hi[2]) != (0.0, 0.0, g.length, g.length):
+            raise ValueError("a steady field covers the unit cell [0, P) x [0, P)")
+        P.field_n[0], P.field_n[1] = int(tl.grid[0]), int(tl.grid[2])
+        P.field_lo[0], P.field_lo[1] = 0.0, 0.0
+        P.field_hi[0], P.field_hi[1] = float(g.length), float(g.length)
     P.seed = int(job.seed)
     rg = getattr(tl, "region", None)
     if rg is not None:
@@ -360,6 +370,9 @@ def split_raw(prep: Prepared, raw: np.ndarray) -> Dict[str, np.ndarray]:
     out["snap_abs"] = raw[o:o + nt * (ncell + 1)].reshape(nt, ncell + 1); o += nt * (ncell + 1)
     if getattr(tl, "region", None) is not None and nt:
         out["region"] = raw[o:o + 4 * nt].reshape(nt, 4); o += 4 * nt
+    if prep.steady and tl.grid[0] > 0:
+        nx, nz = int(tl.grid[0]), int(tl.grid[2])
+        out["field"] = raw[o:o + B * 2 * nx * nz].reshape(B, 2, nz, nx); o += B * 2 * nx * nz
     return out
 
 
@@ -409,6 +422,19 @@ def finalize(prep: Prepared, raw: np.ndarray, N: Optional[int] = None) -> Dict[s
             hv = np.maximum(h2 / N - hm * hm, 0.0)
             res["hj"] = -f * hm
             res["hj_se"] = abs(f) * np.sqrt(hv / max(N - 1, 1))
+    if "field" in parts:
+        # steady field (Eq. (4) per cell, per unit length along y): T = E_dot sum(s t_c) / (A_c C_tot),
+        # q_z = E_dot sum(s v Omega_z t_c) / A_c with A_c the full cell area; batch means for the SE
+        nz, nx = parts["field"].shape[2:]
+        area = (job.geometry.length / nx) * (job.geometry.length / nz)
+        nbat = batch_counts(N, tl.n_batches)
+        good = nbat > 0
+        for name, q, den in (("field_T", 0, area * prep.C_tot), ("field_q", 1, area)):
+            F = parts["field"][:, q]  # (B, nz, nx)
+            res[name] = prep.power * F.sum(axis=0) / (N * den)
+            per = prep.power * F[good] / (nbat[good][:, None, None] * den)
+            ng = int(good.sum())
+            res[name + "_se"] = per.std(axis=0, ddof=1) / math.sqrt(ng) if ng > 1 else np.full((nz, nx), np.nan)
     if not prep.steady:
         g = np.array(tl.grid, dtype=np.float64)
         vcell = float(np.prod((np.array(tl.grid_hi) - np.array(tl.grid_lo)) / g))

@@ -314,6 +314,10 @@ typedef struct {
      * [0, t_0), [t_0, t_1), ... [t_{n-2}, t_{n-1}) from the snapshot times */
     int32_t region_kind;
     double region_c[2], region_r, region_z[2];
+    /* steady pore cell: field of field_n[0] x field_n[1] cells over
+     * [field_lo, field_hi) in (x, z) (0 cells: none); Eq. (4) in every cell */
+    int32_t field_n[2];
+    double field_lo[2], field_hi[2];
 } oracle_problem;
 
 typedef struct {
@@ -321,7 +325,7 @@ typedef struct {
 } oracle_counters;
 
 /* offsets of the tally sections inside the flat FP64 output buffer */
-typedef struct { size_t bins, kappa, hj, snap, snap_abs, region, total; int64_t ncell; } tally_layout;
+typedef struct { size_t bins, kappa, hj, snap, snap_abs, region, field, total; int64_t ncell; } tally_layout;
 
 static tally_layout layout_of(const oracle_problem *P)
 {
@@ -336,6 +340,8 @@ static tally_layout layout_of(const oracle_problem *P)
     /* per window: sum of each particle's s * (time in region), its square, the
      * same for s * (z displacement in region) */
     t.region = o; o += (P->region_kind && P->n_times > 0) ? (size_t)4 * (size_t)P->n_times : 0;
+    /* per batch: TIME (s t_c) and DISPZ (s v Omega_z t_c) of every field cell, x fastest */
+    t.field = o; o += (size_t)P->n_batches * 2 * (size_t)P->field_n[0] * (size_t)P->field_n[1];
     t.total = o;
     return t;
 }
@@ -572,6 +578,51 @@ static void score_bins(const oracle_problem *P, double *bins, int bt, const part
     }
 }
 
+/* The part [a, b] of u in [0, seg] where c + w u lies in [e0, e1); 0 if none. */
+static int axis_interval(double c, double w, double e0, double e1, double seg, double *a, double *b)
+{
+    if (w == 0.0) {
+        if (!(c >= e0 && c < e1)) return 0;
+        *a = 0.0;
+        *b = seg;
+        return 1;
+    }
+    double ta = (e0 - c) / w, tb = (e1 - c) / w;
+    if (ta > tb) { double t = ta; ta = tb; tb = t; }
+    *a = (ta > 0.0) ? ta : 0.0;
+    *b = (tb < seg) ? tb : seg;
+    return *b > *a;
+}
+
+/* Steady field: Eq. (4) applied to every cell of an x-z grid.  The segment
+ * x + v Omega u, u in [0, seg], spends in cell c the time of the overlap of its
+ * x and z intervals there: TIME_c += s t_c, DISPZ_c += s v Omega_z t_c (batch bt).
+ * Every cell is visited (slow and plain). */
+static void score_field(const oracle_problem *P, double *fld, int bt, const particle *p, double v, double seg)
+{
+    int nx = P->field_n[0], nz = P->field_n[1];
+    double wx = v * p->o[0], wz = v * p->o[2];
+    double *T = fld + ((size_t)bt * 2 + 0) * (size_t)nx * nz;
+    double *D = fld + ((size_t)bt * 2 + 1) * (size_t)nx * nz;
+    for (int iz = 0; iz < nz; ++iz) {
+        double z0 = P->field_lo[1] + (P->field_hi[1] - P->field_lo[1]) * iz / nz;
+        double z1 = P->field_lo[1] + (P->field_hi[1] - P->field_lo[1]) * (iz + 1) / nz;
+        double za, zb;
+        if (!axis_interval(p->x[2], wz, z0, z1, seg, &za, &zb)) continue;
+        for (int ix = 0; ix < nx; ++ix) {
+            double x0 = P->field_lo[0] + (P->field_hi[0] - P->field_lo[0]) * ix / nx;
+            double x1 = P->field_lo[0] + (P->field_hi[0] - P->field_lo[0]) * (ix + 1) / nx;
+            double xa, xb;
+            if (!axis_interval(p->x[0], wx, x0, x1, seg, &xa, &xb)) continue;
+            double a = (xa > za) ? xa : za, b = (xb < zb) ? xb : zb;
+            if (b > a) {
+                T[(size_t)iz * nx + ix] += p->s * (b - a);
+                D[(size_t)iz * nx + ix] += p->s * wz * (b - a);
+            }
+        }
+    }
+}
+
 /* Transient estimator (Eq. (3)) at the snapshot times inside [ta, ta + seg):
  * the particle's position there, by linear interpolation along the segment,
  * selects the grid cell (or the overflow slot) that receives s. */
@@ -696,6 +747,7 @@ int oracle_run(const oracle_problem *P, uint64_t pid0, uint64_t pid1, double *ta
             double seg = boundary ? tb : dt;
             /* step V: sample the segment */
             if (P->n_bins > 0) score_bins(P, tally + lay.bins, bt, &p, v, tau_m, seg);
+            if (P->field_n[0] > 0) score_field(P, tally + lay.field, bt, &p, v, seg);
             double dz = p.s * v * p.o[2] * seg;
             Lz += dz;
             if (h && nscat < (uint32_t)P->n_hj) h[nscat] += dz;

@@ -472,3 +472,70 @@ def test_region_tally_ballistic_limit():
         assert np.all(se < teeth * np.abs(ref)), (key, se, ref)
         assert np.all(np.abs(got - ref) <= 4.0 * se + 2e-3 * np.abs(ref)), (key, got, ref, se)
     assert np.all(res["region_q"] > 0.0)  # heat flows into the substrate
+
+
+# ------------------------------------------------------- steady x-z field ----
+
+def _field_job(mat, porosity, n, seed, nx=12, nz=12, period=100e-9):
+    return di.pore_cell(period, porosity, n, seed, material=mat, kmax=40, n_hj=0, field=(nx, nz))
+
+
+def test_field_adds_up_to_the_conductivity_sums():
+    """The field's z displacement over all cells equals the per-particle algebraic
+    lengths of the conductivity estimator (two separate accumulations of the same
+    segments), and its cell-averaged flux is kappa |G|."""
+    mat = di.silicon_like()
+    job = _field_job(mat, 0.2, 20_000, 701)
+    prep = oracle.prepare(job)
+    raw, *_ = oracle.run_raw(job, threads=THREADS, prep=prep)
+    parts = oracle.split_raw(prep, raw)
+    dz = parts["field"][:, 1].sum()
+    assert abs(dz - parts["kappa"][0]) <= 1e-12 * abs(parts["kappa"][0])
+    res = oracle.finalize(prep, raw)
+    assert abs(res["field_q"].mean() - res["kappa"] * abs(job.source.gradient)) <= 1e-10 * abs(res["kappa"] * 1e6)
+    # no time is spent inside the pore: the cells wholly inside it stay empty
+    P, r = job.geometry.length, job.geometry.radius
+    c = (np.arange(12) + 0.5) * P / 12
+    far = np.hypot(*np.meshgrid(c - P / 2, c - P / 2)) + P / 12 * math.sqrt(0.5) < r
+    assert far.any() and np.all(parts["field"][:, :, far] == 0.0)
+
+
+def test_field_bulk_limit():
+    """A cell without a pore is translation invariant: every cell's z heat flux is
+    kappa_bulk |G| and its deviational temperature is zero (any truncation)."""
+    mat = di.gray_material()
+    _, _, _, kb = _kappa_bulk(mat)
+    job = di.pore_cell(200e-9, 0.0, 100_000, 702, material=mat, kmax=10, n_hj=0, field=(8, 8))
+    res, *_ = oracle.simulate(job, threads=THREADS)
+    G = abs(job.source.gradient)
+    zq = (res["field_q"] - kb * G) / res["field_q_se"]
+    zt = res["field_T"] / res["field_T_se"]
+    assert np.all(res["field_q_se"] < 0.1 * kb * G)
+    # chi-square over the 64 cells, 99.9 % quantile (batch-mean SEs over 16 batches: t-tails)
+    for z in (zq, zt):
+        assert np.all(np.abs(z) < 6.0), z
+        assert float(np.sum(z ** 2)) < stats.chi2.ppf(0.999, z.size) * 1.5, z
+
+
+def test_field_symmetries_of_the_pore_cell():
+    """The cell is mirror symmetric in x and in z, and the gradient is along z: the
+    temperature is even in x and odd in z, the z heat flux even in both."""
+    mat = di.silicon_like()
+    res, *_ = oracle.simulate(_field_job(mat, 0.3, 60_000, 703), threads=THREADS)
+    T, Ts, q, qs = res["field_T"], res["field_T_se"], res["field_q"], res["field_q_se"]
+    ok = Ts > 0  # cells inside the pore hold nothing
+    Ts, qs = np.where(ok, Ts, 1.0), np.where(ok, qs, 1.0)
+    checks = [
+        ((T - T[:, ::-1]) / np.hypot(Ts, Ts[:, ::-1]), "T even in x"),
+        ((T + T[::-1, :]) / np.hypot(Ts, Ts[::-1, :]), "T odd in z"),
+        ((q - q[:, ::-1]) / np.hypot(qs, qs[:, ::-1]), "q even in x"),
+        ((q - q[::-1, :]) / np.hypot(qs, qs[::-1, :]), "q even in z"),
+    ]
+    for z, what in checks:
+        zz = z[ok & ok[:, ::-1] & ok[::-1, :]]
+        assert np.all(np.abs(zz) < 6.0), what
+        # each pair appears twice; chi-square of the independent half
+        assert float(np.sum(zz ** 2)) / 2 < stats.chi2.ppf(0.999, zz.size // 2) * 1.5, what
+    # the temperature field is resolved: odd in z with a clear sign on the lower and upper halves
+    lower, upper = T[:6][ok[:6]].mean(), T[6:][ok[6:]].mean()
+    assert lower * upper < 0
