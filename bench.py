@@ -146,6 +146,18 @@ def other_workloads(b, di, mat, mat_in, stream):
                      "capped": sum(s.capped for s in st), "launch": params, "autotune_s": tune_s}
         log(f"{name}: {sc:.3e} scatters in {ms:.1f} ms ({sc / (ms / 1e3):.3e} /s), params {params}")
         r.close()
+    # the steady temperature and heat-flux fields of a pore cell (32 x 32 cells), against
+    # the same cell with only its conductivity tallied
+    fr = {}
+    for tag, field in (("kappa_only", None), ("field_32x32", (32, 32))):
+        jobs = [di.pore_cell(100e-9, 0.3, 20_000_000, seed=1108, material=mat_in, kmax=40, n_hj=0, field=field)]
+        params = launch_params(jobs, mat, stream=stream)
+        r = b.simulate(jobs, material=mat, stream=stream, **params)
+        st = r.stats(0)
+        fr[tag] = {"kernel_ms": st.kernel_ms, "flights_per_s": st.iterations / (st.kernel_ms / 1e3), "launch": params}
+        r.close()
+    res["pore_cell_100nm_phi0.3_2e7_fields"] = fr
+    log(f"pore cell fields 32x32: {fr['field_32x32']['kernel_ms']:.1f} ms against {fr['kappa_only']['kernel_ms']:.1f} ms")
     # the same 64 instances with K_max planned per instance from a pilot run
     # (tail of <H_j> cut where its fitted sum is below 0.2 standard errors)
     jobs = di.batched_nanostructures(material=mat_in)

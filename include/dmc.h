@@ -138,8 +138,12 @@ typedef struct {
     int32_t n_batches; /* batch replicas for standard errors, batch = pid mod n_batches; 2..256 */
     int32_t kmax;      /* stop a particle after kmax scattering events; -1 = never */
     int32_t n_hj;      /* per-scatter-index flux contributions H_j, j < n_hj (<= kmax); 0 = off */
-    int32_t grid[3];   /* transient snapshot grid cells along x, y, z */
-    double grid_lo[3]; /* snapshot grid bounds [m] */
+    int32_t grid[3];   /* transient jobs: snapshot grid cells along x, y, z.  Steady pore cells
+                          (DMC_GEOM_PORE_CELL_XZ): (nx, 1, nz) adds the steady temperature and
+                          z heat-flux fields, Eq. (4) in every cell of an nx x nz grid over the
+                          unit cell (grid_lo x, z = 0, grid_hi x, z = period; y bounds unused),
+                          read as DMC_Q_FIELD_T / DMC_Q_FIELD_QZ; nx, nz <= 1024.  0 = none. */
+    double grid_lo[3]; /* grid bounds [m] */
     double grid_hi[3];
     int32_t first_event; /* in-plane films (DMC_GEOM_FILM_X, gradient source) only: 1 ends every
                             trajectory at its first scattering event or first diffuse wall
@@ -321,6 +325,9 @@ dmc_status dmc_plan_truncation(const dmc_job *job, const dmc_run_opts *opts, con
 #define DMC_Q_RAW 7        /* the job's raw FP64 tally block (n = dmc_tally_raw_size) */
 #define DMC_Q_REGION_T 8   /* windowed mean T - T_eq in the region, one per window [K] (n = n_times) */
 #define DMC_Q_REGION_QZ 9  /* windowed mean z heat flux in the region [W/m^2] (n = n_times) */
+#define DMC_Q_FIELD_T 10   /* steady pore cell: T - T_eq per field cell [K] (n = nx * nz, x fastest;
+                              energy over the whole cell area, pore included) */
+#define DMC_Q_FIELD_QZ 11  /* steady pore cell: z heat flux per field cell [W/m^2] (same layout) */
 
 /* Waits for the launch, then writes n values of `quantity` of job `job` (and,
  * if stderr_out is not NULL, their standard errors: batch means for bins,

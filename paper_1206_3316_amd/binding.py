@@ -23,7 +23,8 @@ WALL = {"isothermal": 0, "adiabatic": 1, "periodic": 2}
 SRC = {"walls": 0, "gaussian": 1, "gradient": 2}
 PREC = {"fp64": 0, "fp32": 1}
 FORM = {"plain": 0, "persistent": 1}
-Q_T, Q_TLOC, Q_FLUX, Q_KAPPA, Q_HJ, Q_SNAPSHOT, Q_SNAPSHOT_SUM, Q_RAW, Q_REGION_T, Q_REGION_QZ = range(10)
+(Q_T, Q_TLOC, Q_FLUX, Q_KAPPA, Q_HJ, Q_SNAPSHOT, Q_SNAPSHOT_SUM, Q_RAW, Q_REGION_T, Q_REGION_QZ,
+ Q_FIELD_T, Q_FIELD_QZ) = range(12)
 TABLE_GAIN, TABLE_INIT, TABLE_FLUX = 0, 1, 2
 
 f64p = C.POINTER(C.c_double)
@@ -439,6 +440,8 @@ class Result:
                 n = int(np.prod(jb.tally.grid)) + 1
             elif quantity in (Q_REGION_T, Q_REGION_QZ):
                 n = len(jb.tally.times)
+            elif quantity in (Q_FIELD_T, Q_FIELD_QZ):
+                n = int(jb.tally.grid[0]) * int(jb.tally.grid[2])
             else:
                 raise ValueError("give n for this quantity")
         mean = np.zeros(max(n, 1))

@@ -201,6 +201,7 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
     d.n_times = jb.n_times;
     d.lds_bins = d.lds_kappa = d.lds_hj = -1;
     d.off_bins = d.off_kappa = d.off_hj = d.off_snap = d.off_snap_abs = d.off_dispx = d.off_region = -1;
+    d.off_field = -1;
     d.lds_dispx = d.lds_region = -1;
     d.disp_tel = 0;
     if ((g.kind == DMC_GEOM_SLAB_Z || g.kind == DMC_GEOM_FILM_X) && t.n_bins > 0) {
@@ -311,6 +312,25 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
         d.region_r = t.region_radius;
         d.region_z[0] = t.region_z[0];
         d.region_z[1] = t.region_z[1];
+    }
+    if (!transient && (t.grid[0] != 0 || t.grid[1] != 0 || t.grid[2] != 0)) {
+        // steady x-z field over the pore cell (Eq. (4) per cell), batch replicas for the SE
+        if (g.kind != DMC_GEOM_PORE_CELL_XZ)
+            return fail(DMC_E_INVALID, "a steady field needs a pore-cell geometry (or set grid to 0)");
+        if (t.grid[0] < 1 || t.grid[0] > 1024 || t.grid[2] < 1 || t.grid[2] > 1024 || t.grid[1] != 1)
+            return fail(DMC_E_INVALID, "steady field grid must be (nx, 1, nz) with 1 <= nx, nz <= 1024");
+        if (t.grid_lo[0] != 0.0 || t.grid_lo[2] != 0.0 || t.grid_hi[0] != g.length || t.grid_hi[2] != g.length)
+            return fail(DMC_E_INVALID, "a steady field covers the unit cell: grid_lo x, z = 0, grid_hi x, z = period");
+        for (int i = 0; i < 3; i += 2) {
+            d.grid[i] = t.grid[i];
+            d.grid_lo[i] = 0.0;
+            d.grid_ext[i] = g.length;
+            d.grid_lof[i] = 0.0f;
+            d.grid_scf[i] = (float)((double)t.grid[i] / g.length);
+        }
+        d.grid[1] = 1;
+        d.off_field = o;
+        o += (int64_t)t.n_batches * 2 * t.grid[0] * t.grid[2];
     }
     if (t.n_bins > 0) {  // last: the visible block stays contiguous
         // hidden: not part of the raw block a caller reads (the host folds it into
@@ -635,6 +655,7 @@ dmc_status gather_jobs(const dmc_job *jobs, int32_t n_jobs, std::vector<JobHost>
         if (d.off_snap_abs >= 0) d.off_snap_abs += toff;
         if (d.off_dispx >= 0) d.off_dispx += toff;
         if (d.off_region >= 0) d.off_region += toff;
+        if (d.off_field >= 0) d.off_field += toff;
         toff += jh[i].size;
         d.times_off = (int32_t)tim;
         tim += (int64_t)jh[i].times.size();
@@ -1018,6 +1039,44 @@ extern "C" dmc_status dmc_tally_read(const dmc_result *cres, int32_t job, int32_
                 const double m = s1 / N;
                 const double var = std::max(s2 / N - m * m, 0.0) * N / std::max(N - 1.0, 1.0);
                 se[j] = e_eff * std::sqrt(N * var) / (tw * den);
+            }
+        }
+        return DMC_OK;
+    }
+    if (q == DMC_Q_FIELD_T || q == DMC_Q_FIELD_QZ) {
+        // E_dot sum(s t_c) / (A_c C_tot) and E_dot sum(s v Omega_z t_c) / A_c per unit length
+        // along y, A_c the whole cell area; batch means for the SE
+        if (d.off_field < 0) return fail(DMC_E_INVALID, "no field tallied");
+        const int nx = d.grid[0], nz = d.grid[2];
+        const int64_t nc = (int64_t)nx * nz;
+        if (n < (size_t)nc) return fail(DMC_E_INVALID, "output too small");
+        const int qi = (q == DMC_Q_FIELD_T) ? 0 : 1;
+        const double area = (d.grid_ext[0] / nx) * (d.grid_ext[2] / nz);
+        const double norm = h.power / (qi == 0 ? area * M.C_tot : area);
+        const int B = d.n_batches;
+        for (int64_t c = 0; c < nc; ++c) {
+            double tot = 0.0;
+            std::vector<double> per;
+            for (int b = 0; b < B; ++b) {
+                const double v = T[d.off_field + ((int64_t)b * 2 + qi) * nc + c];
+                tot += v;
+                const double nb = (d.n > (uint64_t)b) ? (double)((d.n - b + B - 1) / B) : 0.0;
+                if (nb > 0) per.push_back(v * norm / nb);
+            }
+            mean[c] = tot * norm / N;
+            if (se) {
+                const size_t m = per.size();
+                if (m < 2) {
+                    se[c] = NAN;
+                } else {
+                    double mu = 0.0;
+                    for (double x : per) mu += x;
+                    mu /= (double)m;
+                    double var = 0.0;
+                    for (double x : per) var += (x - mu) * (x - mu);
+                    var /= (double)(m - 1);
+                    se[c] = std::sqrt(var / (double)m);
+                }
             }
         }
         return DMC_OK;

@@ -217,6 +217,7 @@ struct Lane {
     int32_t rwin;
     double rt, rq;
     double rwbeg, rwend;
+    int32_t fld;            // the job tallies the steady x-z field (gradient and generic kernels)
 };
 
 struct Shared {
@@ -341,6 +342,7 @@ __device__ __forceinline__ void bind_job(Lane<R> &p, const JobDev &J, uint64_t p
     p.rwin = -1;
     p.rt = p.rq = 0.0;
     p.pend = -1;
+    p.fld = (G == GEOM_GRAD || G == GEOM_ANY) ? (J.off_field >= 0 ? 1 : 0) : 0;
     {
         const int32_t boff = p.batch * 3 * p.n_bins;
         p.bl = (J.lds_bins >= 0) ? J.lds_bins + boff : -1;
@@ -707,6 +709,75 @@ __device__ void score_snapshots(Lane<R> &p, const KArgs &a, const JobDev &J, dou
         }
         ++p.tcur;
         p.tnext = (p.tcur < p.n_times) ? times[p.tcur] : __builtin_huge_val();
+    }
+}
+
+// Edge i of the steady field along an axis of n cells over [0, P): P i / n,
+// evaluated as the FP64 reference does (FP32 kernels: i times the FP32 width).
+template <typename R>
+__device__ __forceinline__ R field_edge(int i, int n, double P, R width)
+{
+    if constexpr (sizeof(R) == 8) return P * (double)i / (double)n;
+    return (R)i * width;
+}
+
+// Cell of coordinate c along an axis (the cell whose [edge i, edge i+1) holds c,
+// clamped), from a first guess corrected against the edges themselves.
+template <typename R>
+__device__ __forceinline__ int field_cell(R c, int n, double P, R width)
+{
+    int i = (int)(c * (R)n / (R)P);
+    i = min(max(i, 0), n - 1);
+    if (i > 0 && c < field_edge<R>(i, n, P, width)) --i;
+    if (i < n - 1 && c >= field_edge<R>(i + 1, n, P, width)) ++i;
+    return i;
+}
+
+// Steady x-z field of the pore cell: Eq. (4) in every cell of the grid.  The
+// segment from (x, z) along (wx, wz) = v (Omega_x, Omega_z), u in [0, seg], is
+// walked cell by cell: the current cell is left at the earlier of its x and z
+// exit times (edge - c) / w, and it holds the segment from its entry time to
+// that exit (or seg).  These are the interval ends the FP64 reference computes
+// cell by cell, so both give every cell the same time.  TIME_c += s t_c and
+// DISPZ_c += s wz t_c go straight to the launch's tally buffer (batch of the
+// particle); the grid is too large to privatise.
+template <typename R>
+__device__ void score_field(const Lane<R> &p, const KArgs &a, const JobDev &J, R seg)
+{
+    const int nx = J.grid[0], nz = J.grid[2];
+    const double P = J.grid_ext[0];
+    const R cwx = (R)(P / nx), cwz = (R)(P / nz);
+    const R wx = p.v * p.ox, wz = p.v * p.oz;
+    int ix = field_cell<R>(p.x, nx, P, cwx), iz = field_cell<R>(p.z, nz, P, cwz);
+    const int64_t nc = (int64_t)nx * nz;
+    double *base = a.tally + J.off_field + (int64_t)p.batch * 2 * nc;
+    const double sg = (double)p.s;
+    R t0 = (R)0;
+    for (int it = 0; it < nx + nz + 2; ++it) {  // a segment inside the cell visits at most nx + nz cells
+        R tx = Pr<R>::inf(), tz = Pr<R>::inf();
+        if (wx > (R)0)
+            tx = Pr<R>::div(field_edge<R>(ix + 1, nx, P, cwx) - p.x, wx);
+        else if (wx < (R)0)
+            tx = Pr<R>::div(field_edge<R>(ix, nx, P, cwx) - p.x, wx);
+        if (wz > (R)0)
+            tz = Pr<R>::div(field_edge<R>(iz + 1, nz, P, cwz) - p.z, wz);
+        else if (wz < (R)0)
+            tz = Pr<R>::div(field_edge<R>(iz, nz, P, cwz) - p.z, wz);
+        R t1 = tx < tz ? tx : tz;
+        if (seg < t1) t1 = seg;
+        if (t1 > t0) {
+            const int64_t c = (int64_t)iz * nx + ix;
+            const double dt = (double)(t1 - t0);
+            gadd(base + c, sg * dt);
+            gadd(base + nc + c, sg * (double)wz * dt);
+        }
+        if (!(t1 < seg)) break;
+        if (tx <= tz)
+            ix += (wx > (R)0) ? 1 : -1;
+        else
+            iz += (wz > (R)0) ? 1 : -1;
+        if (ix < 0 || ix >= nx || iz < 0 || iz >= nz) break;
+        if (t1 > t0) t0 = t1;
     }
 }
 
@@ -1096,6 +1167,9 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
     const R seg = boundary ? tb : dt;
     // step V: sample the segment
     if (G == GEOM_SLAB || p.n_bins > 0) score_bins<R, FORM, G>(p, a, sh, J, seg);  // the slab kernel always has bins
+    if constexpr (G == GEOM_GRAD || G == GEOM_ANY) {
+        if (p.fld) score_field(p, a, J, seg);
+    }
     const bool gradient = (G == GEOM_GRAD) || ((G == GEOM_ANY) && (p.src == SRC_GRADIENT));
     if (gradient) {
         const double dz = (double)(p.s * p.v * p.oz * seg);

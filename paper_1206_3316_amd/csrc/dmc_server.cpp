@@ -256,6 +256,7 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
             if (d.off_snap_abs >= 0) d.off_snap_abs += shift;
             if (d.off_dispx >= 0) d.off_dispx += shift;
             if (d.off_region >= 0) d.off_region += shift;
+            if (d.off_field >= 0) d.off_field += shift;
             d.base = base;
             d.n = n;
             d.pid0 = r->jh.dev.pid0 + r->cursor;

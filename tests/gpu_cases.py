@@ -53,6 +53,7 @@ def parity_cases():
         "pore_cell": di.pore_cell(100e-9, 0.3, 20_000, seed=105, material=si, kmax=40, n_hj=40),
         "pore_cell_specular": di.pore_cell(80e-9, 0.2, 10_000, seed=106, material=gray, kmax=20, n_hj=5,
                                            specularity=0.7),
+        "pore_field": di.pore_cell(100e-9, 0.3, 20_000, seed=108, material=si, kmax=40, n_hj=8, field=(12, 10)),
         "periodic_film": periodic_slab(),
         "spot": small_spot(),
         "spot_region": spot_region(),
@@ -84,6 +85,11 @@ def lib_sections(job, raw):
         if getattr(t, "region", None) is not None:
             out["region"] = raw[o:o + 4 * nt].reshape(nt, 4)
             o += 4 * nt
+    elif t.grid[0] > 0:  # steady pore-cell field [batch][TIME, DISPZ][nz][nx]
+        nx, nz = int(t.grid[0]), int(t.grid[2])
+        n = t.n_batches * 2 * nx * nz
+        out["field"] = raw[o:o + n].reshape(t.n_batches, 2, nz, nx)
+        o += n
     assert o == raw.shape[0], (o, raw.shape)
     return out
 
@@ -113,6 +119,9 @@ def compare_sections(lib_s, orc_s, rel, vmax=None):
                 if q == 2 and vmax is not None:
                     scale = max(scale, 1e-3 * vmax * np.abs(ref[:, 0, :]).max())
                 worst[f"bins{q}"] = float(d / max(scale, 1e-300))
+        elif k == "field":
+            for q, name in ((0, "field_time"), (1, "field_dispz")):
+                worst[name] = rel_diff(v[:, q], ref[:, q])
         elif k == "region":
             # per window: time and z length in the region, each with its square
             for col, name in enumerate(("region_t", "region_t2", "region_q", "region_q2")):

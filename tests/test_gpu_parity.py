@@ -181,6 +181,20 @@ def test_fp32_production_within_tolerance(name, oracle_runs):
             for q, key in ((b.Q_REGION_T, "region_T"), (b.Q_REGION_QZ, "region_q")):
                 m, se = res.read(0, q)
                 _assert_stat_close(name, key, m, se, ores[key], ores[key + "_se"])
+    elif t.grid[0] > 0:
+        # steady field: pore cells are chaotic billiards, so the FP32 and FP64 realisations
+        # separate and the cells agree statistically; over ~100 cells the 3-SE rule is
+        # taken as a Bonferroni-safe |z| < 4.5 and a chi-square bound
+        for q, key in ((b.Q_FIELD_T, "field_T"), (b.Q_FIELD_QZ, "field_q")):
+            m, se = res.read(0, q)
+            ref, rse = ores[key].ravel(), ores[key + "_se"].ravel()
+            comb = np.hypot(se, rse)
+            live = comb > 0
+            assert np.array_equal(m[~live], ref[~live])  # cells inside the pore hold nothing on both sides
+            z = (m[live] - ref[live]) / comb[live]
+            print(f"fp32-vs-oracle {name} {key}: max |z| {np.abs(z).max():.2f} over {z.size} cells", flush=True)
+            assert np.all(np.abs(z) < 4.5), (key, z)
+            assert float(np.sum(z ** 2)) < 1.5 * z.size + 5.0 * math.sqrt(2.0 * z.size), (key, z)
     st = res.stats(0)
     assert st.particles == job.n_particles and st.capped == 0
 
@@ -285,6 +299,18 @@ def small_spot_job():
 
 def test_invalid_jobs_are_rejected():
     si = di.silicon_like()
+    # steady fields: pore cells only, grid (nx, 1, nz), bounds the unit cell
+    slab = di.slab_job(si, 100e-9, 10, seed=1)
+    slab.tally.grid, slab.tally.grid_hi = (4, 1, 4), (1e-7, 1.0, 1e-7)
+    pore = di.pore_cell(100e-9, 0.2, 10, seed=1, material=si, field=(4, 4))
+    thick = di.pore_cell(100e-9, 0.2, 10, seed=1, material=si, field=(4, 4))
+    thick.tally.grid = (4, 2, 4)
+    shifted = di.pore_cell(100e-9, 0.2, 10, seed=1, material=si, field=(4, 4))
+    shifted.tally.grid_hi = (50e-9, 1.0, 100e-9)
+    for bad in (slab, thick, shifted):
+        with pytest.raises(b.DmcError):
+            b.simulate([bad])
+    assert b.simulate([pore]).stats(0).particles == 10
     job = di.slab_job(si, 100e-9, 10, seed=1)
     job.tally.n_hj = 3  # needs kmax
     with pytest.raises(b.DmcError):

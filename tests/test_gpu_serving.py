@@ -25,6 +25,7 @@ def _requests(si):
         di.slab_job(si, 1e-6, 5_000, seed=2004, n_bins=20),
         di.in_plane_film(50e-9, 0.5, 25_000, seed=2005, material=si, kmax=40, n_hj=4),
         di.slab_job(si, 3e-8, 60_000, seed=2006, n_bins=20),
+        di.pore_cell(90e-9, 0.2, 15_000, seed=2009, material=si, kmax=40, n_hj=4, field=(8, 8)),
     ]
 
 
