@@ -202,6 +202,7 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
     d.lds_bins = d.lds_kappa = d.lds_hj = -1;
     d.off_bins = d.off_kappa = d.off_hj = d.off_snap = d.off_snap_abs = d.off_dispx = d.off_region = -1;
     d.off_field = -1;
+    d.lds_field = -1;
     d.lds_dispx = d.lds_region = -1;
     d.disp_tel = 0;
     if ((g.kind == DMC_GEOM_SLAB_Z || g.kind == DMC_GEOM_FILM_X) && t.n_bins > 0) {
@@ -447,7 +448,7 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
     if (b.n_resume && !b.drain_iters) return fail(DMC_E_INVALID, "resuming needs a time-bounded launch");
     const size_t stats_lds = a.lds_stats ? (size_t)n_jobs * kStats * 8 : 0;
     for (auto &d : devs) {
-        d.lds_bins = d.lds_kappa = d.lds_hj = d.lds_dispx = d.lds_region = -1;
+        d.lds_bins = d.lds_kappa = d.lds_hj = d.lds_dispx = d.lds_region = d.lds_field = -1;
         d.disp_tel = (o.form == DMC_FORM_PERSISTENT && spec == GEOM_SLAB && !(b.drain_iters || b.n_resume)) ? 1 : 0;
     }
     int block = 256, grid = 1;
@@ -484,6 +485,15 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
                 if (d.off_region >= 0 && (size_t)(lo + 4 * d.n_times) <= budget) {
                     d.lds_region = lo;
                     lo += 4 * d.n_times;
+                }
+            }
+            // fields last: they are large, and the small sections of every job come first
+            for (auto &d : devs) {
+                if (d.off_field < 0) continue;
+                const int64_t n = (int64_t)d.n_batches * 2 * d.grid[0] * d.grid[2];
+                if ((size_t)(lo + n) <= budget) {
+                    d.lds_field = lo;
+                    lo += (int32_t)n;
                 }
             }
         }

@@ -60,7 +60,9 @@ struct alignas(16) JobDev {
     int32_t lds_region;     // -1: in global memory
     int64_t off_region;     // windowed region tally [n_times][4]: sum v_T, v_T^2, v_Q, v_Q^2 (-1: none)
     double region_c[2], region_r, region_z[2];
-    int64_t off_field;      // steady pore-cell field [batch][TIME, DISPZ][nz][nx] in global memory (-1: none)
+    int64_t off_field;      // steady pore-cell field [batch][TIME, DISPZ][nz][nx] (-1: none)
+    int32_t lds_field;      // -1: accumulated in global memory
+    int32_t pad_field;
 };
 
 // A particle suspended at the end of a time-bounded launch (serving epochs):

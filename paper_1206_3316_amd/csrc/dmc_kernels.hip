@@ -739,18 +739,17 @@ __device__ __forceinline__ int field_cell(R c, int n, double P, R width)
 // exit times (edge - c) / w, and it holds the segment from its entry time to
 // that exit (or seg).  These are the interval ends the FP64 reference computes
 // cell by cell, so both give every cell the same time.  TIME_c += s t_c and
-// DISPZ_c += s wz t_c go straight to the launch's tally buffer (batch of the
-// particle); the grid is too large to privatise.
+// DISPZ_c += s wz t_c go to the particle's batch of the field, privatised in LDS when it fits, else global FP64 atomics.
 template <typename R>
-__device__ void score_field(const Lane<R> &p, const KArgs &a, const JobDev &J, R seg)
+__device__ void score_field(const Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, R seg)
 {
     const int nx = J.grid[0], nz = J.grid[2];
     const double P = J.grid_ext[0];
     const R cwx = (R)(P / nx), cwz = (R)(P / nz);
     const R wx = p.v * p.ox, wz = p.v * p.oz;
     int ix = field_cell<R>(p.x, nx, P, cwx), iz = field_cell<R>(p.z, nz, P, cwz);
-    const int64_t nc = (int64_t)nx * nz;
-    double *base = a.tally + J.off_field + (int64_t)p.batch * 2 * nc;
+    const int32_t nc = nx * nz;
+    const int32_t b0 = p.batch * 2 * nc;
     const double sg = (double)p.s;
     R t0 = (R)0;
     for (int it = 0; it < nx + nz + 2; ++it) {  // a segment inside the cell visits at most nx + nz cells
@@ -766,10 +765,10 @@ __device__ void score_field(const Lane<R> &p, const KArgs &a, const JobDev &J, R
         R t1 = tx < tz ? tx : tz;
         if (seg < t1) t1 = seg;
         if (t1 > t0) {
-            const int64_t c = (int64_t)iz * nx + ix;
+            const int32_t c = iz * nx + ix;
             const double dt = (double)(t1 - t0);
-            gadd(base + c, sg * dt);
-            gadd(base + nc + c, sg * (double)wz * dt);
+            tadd(a, sh, J.lds_field, J.off_field, b0 + c, sg * dt);
+            tadd(a, sh, J.lds_field, J.off_field, b0 + nc + c, sg * (double)wz * dt);
         }
         if (!(t1 < seg)) break;
         if (tx <= tz)
@@ -1168,7 +1167,7 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
     // step V: sample the segment
     if (G == GEOM_SLAB || p.n_bins > 0) score_bins<R, FORM, G>(p, a, sh, J, seg);  // the slab kernel always has bins
     if constexpr (G == GEOM_GRAD || G == GEOM_ANY) {
-        if (p.fld) score_field(p, a, J, seg);
+        if (p.fld) score_field(p, a, sh, J, seg);
     }
     const bool gradient = (G == GEOM_GRAD) || ((G == GEOM_ANY) && (p.src == SRC_GRADIENT));
     if (gradient) {
@@ -1307,6 +1306,13 @@ __device__ void flush_shared(const KArgs &a, const Shared &sh)
                 for (int i = threadIdx.x; i < 2 * J.n_hj; i += blockDim.x) {
                     const double v = sh.ltally[J.lds_hj + i];
                     if (v != 0.0) gadd(a.tally + J.off_hj + i, v);
+                }
+            }
+            if (J.lds_field >= 0) {
+                const int n = J.n_batches * 2 * J.grid[0] * J.grid[2];
+                for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                    const double v = sh.ltally[J.lds_field + i];
+                    if (v != 0.0) gadd(a.tally + J.off_field + i, v);
                 }
             }
         }
