@@ -146,18 +146,20 @@ def other_workloads(b, di, mat, mat_in, stream):
                      "capped": sum(s.capped for s in st), "launch": params, "autotune_s": tune_s}
         log(f"{name}: {sc:.3e} scatters in {ms:.1f} ms ({sc / (ms / 1e3):.3e} /s), params {params}")
         r.close()
-    # the steady temperature and heat-flux fields of a pore cell (32 x 32 cells), against
-    # the same cell with only its conductivity tallied
+    # the steady temperature and heat-flux fields of a pore cell (16 x 16 cells privatised in
+    # LDS, 32 x 32 in global memory), against the same cell with only its conductivity
+    # tallied; the nanostructure batch's launch parameters
     fr = {}
-    for tag, field in (("kappa_only", None), ("field_32x32", (32, 32))):
+    for tag, field in (("kappa_only", None), ("field_16x16", (16, 16)), ("field_32x32", (32, 32))):
         jobs = [di.pore_cell(100e-9, 0.3, 20_000_000, seed=1108, material=mat_in, kmax=40, n_hj=0, field=field)]
-        params = launch_params(jobs, mat, stream=stream)
+        params = {"block": 0, "chunk": 1024, "refill_min": 16, "lds_tally": 1}
         r = b.simulate(jobs, material=mat, stream=stream, **params)
         st = r.stats(0)
         fr[tag] = {"kernel_ms": st.kernel_ms, "flights_per_s": st.iterations / (st.kernel_ms / 1e3), "launch": params}
         r.close()
     res["pore_cell_100nm_phi0.3_2e7_fields"] = fr
-    log(f"pore cell fields 32x32: {fr['field_32x32']['kernel_ms']:.1f} ms against {fr['kappa_only']['kernel_ms']:.1f} ms")
+    log(f"pore cell fields: 16x16 {fr['field_16x16']['kernel_ms']:.1f} ms, 32x32 {fr['field_32x32']['kernel_ms']:.1f} ms, "
+        f"without {fr['kappa_only']['kernel_ms']:.1f} ms")
     # the same 64 instances with K_max planned per instance from a pilot run
     # (tail of <H_j> cut where its fitted sum is below 0.2 standard errors)
     jobs = di.batched_nanostructures(material=mat_in)
