@@ -202,7 +202,7 @@ def mix_capacity(b, di, mat, reqs, stream, args, n_sample=64, n_epochs=24):
     3 .. n_epochs (the mix runs the generic kernel in time-bounded epochs)."""
     free, _ = torch_free_bytes()
     srv = b.Server(mat, int(min(0.8 * free, 64 << 30)), max_active=32, epoch_flights=args.epoch_flights,
-                   stream=stream, refill_min=4)
+                   stream=stream, refill_min=4, class_epochs=args.serve_class_epochs)
     for _, j in reqs[:n_sample]:
         srv.submit(j)
     f0 = k0 = 0.0
@@ -229,12 +229,13 @@ def serve(b, di, torch, mat, mat_in, stream, n_requests, args):
     reqs = di.serving_stream(n_requests, material=mat_in)
     work = [j.n_particles * flights_per_particle(j, sums) for _, j in reqs]
     capacity = mix_capacity(b, di, mat, reqs, stream, args)
-    rate = 0.8 * capacity / (sum(work) / len(work))
+    rate = args.serve_rate or 0.8 * capacity / (sum(work) / len(work))
     log(f"serving: mix capacity {capacity:.3e} flights/s, arrival rate {rate:.2f} requests/s")
     arrivals = di.poisson_arrivals(n_requests, rate)
     free, _ = torch.cuda.mem_get_info()
     budget = int(min(0.8 * free, 64 << 30))
-    srv = b.Server(mat, budget, max_active=32, epoch_flights=args.epoch_flights, stream=stream, refill_min=4)
+    srv = b.Server(mat, budget, max_active=32, epoch_flights=args.epoch_flights, stream=stream, refill_min=4,
+                   class_epochs=args.serve_class_epochs)
     lat, kinds, scat = [], [], 0
     pending = {}
     i = 0
@@ -330,6 +331,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=500)
     ap.add_argument("--epoch-flights", type=float, default=2e10)
     ap.add_argument("--serve-max-s", type=float, default=120.0, help="stop admitting requests after this long")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="request arrival rate per second (default: 0.8 x the mix's measured capacity)")
+    ap.add_argument("--serve-class-epochs", action="store_true",
+                    help="epochs take one request class at a time, in that class's specialised kernel")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--only", choices=["spot", "nano"], default=None,
                     help="one launch of the heated spot (1e9, 64^3 x 50) or of the 64 nanostructures, "

@@ -365,13 +365,21 @@ typedef struct {
                                requests (0 = 2e10) */
     uint32_t drain_flights; /* flights a wave may still run once the epoch's queue is empty before
                                it suspends its live particles to the next epoch (0 = 2048) */
+    int32_t class_epochs;  /* 0: every admitted request in every epoch, in the kernel that fits the
+                              epoch's jobs (the generic one once classes mix); 1: each epoch runs
+                              the admitted requests of one class (wall-driven slabs, transient
+                              half spaces, gradient films and pore cells, others), the classes
+                              taking turns, so every epoch uses that class's specialised kernel:
+                              more flights per second, but a request's slowest trajectories
+                              advance only in its class's turns, which lengthens latency */
     dmc_run_opts run;      /* precision / form / stream / parameters of every epoch */
 } dmc_server_opts;
 
 /* The server admits requests while their device memory fits the budget and
- * a slot is free; each epoch is one persistent launch over a slice of every
- * admitted request's particle range, so requests that arrive while others
- * run join at the next epoch.  Epochs are time-bounded: particles still in
+ * a slot is free; each epoch is one persistent launch over a slice of the
+ * particle range of every admitted request (of the epoch's class, see
+ * class_epochs), so requests that arrive while others run join at a later
+ * epoch.  Epochs are time-bounded: particles still in
  * flight when an epoch drains are suspended on the device and resumed first
  * in the next epoch with the same random-number counters, so results do not
  * depend on the slicing.  A request's tallies stay on the device until it

@@ -96,7 +96,7 @@ class dmc_trunc_plan(C.Structure):
 
 class dmc_server_opts(C.Structure):
     _fields_ = [("memory_budget", C.c_size_t), ("max_active", C.c_int32), ("epoch_flights", C.c_uint64),
-                ("drain_flights", C.c_uint32), ("run", dmc_run_opts)]
+                ("drain_flights", C.c_uint32), ("class_epochs", C.c_int32), ("run", dmc_run_opts)]
 
 
 _SIGS = {
@@ -577,12 +577,13 @@ class Server:
     """Continuous-batching server (dmc_server_*): requests share persistent epoch launches."""
 
     def __init__(self, material: Material, memory_budget: int, max_active: int = 32, epoch_flights: float = 2e10,
-                 drain_flights: int = 0, precision="fp32", stream=None, **params):
+                 drain_flights: int = 0, precision="fp32", stream=None, class_epochs: bool = False, **params):
         o = dmc_server_opts()
         o.memory_budget = int(memory_budget)
         o.max_active = int(max_active)
         o.epoch_flights = int(epoch_flights)
         o.drain_flights = int(drain_flights)
+        o.class_epochs = 1 if class_epochs else 0
         o.run = run_opts(precision, "persistent", getattr(stream, "cuda_stream", stream), **params)
         h = C.c_void_p()
         dmc_server_create(material.handle, C.byref(o), C.byref(h))

@@ -506,7 +506,7 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
         a.refill_min = o.refill_min > 0 ? o.refill_min : 16;
         block = o.block > 0 ? o.block : (lds_bytes > 64 * 1024 ? 1024 : 512);
         const bool bounded = b.drain_iters > 0 || b.n_resume > 0;
-        const int per_cu = occupancy_blocks(o.precision, o.form, bounded ? (int)GEOM_ANY : spec, bounded, block, lds_bytes);
+        const int per_cu = occupancy_blocks(o.precision, o.form, spec, bounded, block, lds_bytes);
         grid = o.grid_blocks > 0 ? o.grid_blocks : device_cus() * per_cu;
         if (b.drain_iters) {
             // every lane may suspend one particle and every wave the unstarted rest of

@@ -20,7 +20,9 @@ enum Geom : int32_t { GEOM_SLAB = 0, GEOM_FILM = 1, GEOM_PORE = 2, GEOM_HALF = 3
 // GEOM_GRAD and GEOM_ANY only select kernel specialisations (see kernel_spec).
 enum Wall : int32_t { WALL_ISOTHERMAL = 0, WALL_ADIABATIC = 1, WALL_PERIODIC = 2 };
 enum Src : int32_t { SRC_WALLS = 0, SRC_GAUSSIAN = 1, SRC_GRADIENT = 2 };
-enum Form : int32_t { FORM_PLAIN = 0, FORM_PERSISTENT = 1 };
+// FORM_EPOCH: the persistent form in time-bounded launches (serving epochs),
+// whose particles may be suspended and resumed in a later launch.
+enum Form : int32_t { FORM_PLAIN = 0, FORM_PERSISTENT = 1, FORM_EPOCH = 2 };
 enum Tag : uint32_t { TAG_STEP = 0, TAG_EMIT_A = 1, TAG_EMIT_B = 2 };
 constexpr int32_t kNoSurface = -1;
 

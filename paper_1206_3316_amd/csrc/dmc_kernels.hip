@@ -19,6 +19,10 @@
 //                     refill free lanes; gain table and state data staged in
 //                     LDS; per-lane bin caches flushed to LDS-privatised
 //                     tallies that are added to HBM once per workgroup
+//          EPOCH      the persistent form in time-bounded launches (serving
+//                     epochs): particles are resumed and suspended, and every
+//                     tally is complete within each launch (no telescoping, no
+//                     deferred snapshot scoring)
 //   G      GEOM_SLAB  cross-plane slab, wall sources, steady (dead components
 //                     eliminated)
 //          GEOM_HALF  half space, Gaussian initial condition, snapshots only
@@ -456,7 +460,7 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
 template <typename R, int FORM>
 __device__ __forceinline__ void bins_add(const Lane<R> &p, const KArgs &a, const Shared &sh, int32_t idx, double v)
 {
-    if (FORM == FORM_PERSISTENT && a.bins_lds_all)
+    if (FORM != FORM_PLAIN && a.bins_lds_all)
         atomicAdd(sh.ltally + (p.bl + idx), v);
     else
         tadd(a, sh, p.bl, p.bg, idx, v);
@@ -475,6 +479,8 @@ __device__ constexpr bool defer_snapshots()
 // a continuous path.  Slab particles start and end on a wall, where F_k is 0 (z =
 // 0) or w (z = L) for every bin, so a per-batch count of net transmissions
 // replaces the per-flight displacement sum; the host expands it into the bins.
+// Not in time-bounded launches: a suspended particle may finish in another
+// launch, and the per-flight sums must then be complete in every launch.
 template <int FORM, int G>
 __device__ constexpr bool telescoped()
 {
@@ -501,7 +507,7 @@ __device__ __forceinline__ void flush_entry(Lane<R> &p, const KArgs &a, const Sh
 template <typename R, int FORM, int G>
 __device__ __forceinline__ void bin_flush(Lane<R> &p, const KArgs &a, const Shared &sh)
 {
-    if (FORM != FORM_PERSISTENT) return;  // the plain form adds every contribution directly
+    if (FORM == FORM_PLAIN) return;  // the plain form adds every contribution directly
     flush_entry<R, FORM, G>(p, a, sh, p.cbin, p.c0, p.c1, p.c2);
     if (G == GEOM_SLAB) flush_entry<R, FORM, G>(p, a, sh, p.dbin, p.d0, p.d1, p.d2);
     p.cbin = p.dbin = -1;
@@ -541,7 +547,7 @@ template <typename R, int FORM, int G>
 __device__ __forceinline__ void bin_add(Lane<R> &p, const KArgs &a, const Shared &sh, int k, R t, R vz, bool cached)
 {
     constexpr bool T = telescoped<FORM, G>();
-    if (FORM == FORM_PERSISTENT && cached) {
+    if (FORM != FORM_PLAIN && cached) {
         // unsigned sums: the particle's sign multiplies them when they are added
         p.c0 += (double)t;
         p.c1 += (double)Pr<R>::ptime(t, p.tau, p.itau);
@@ -572,7 +578,7 @@ __device__ void score_bins(Lane<R> &p, const KArgs &a, const Shared &sh, const J
     const R vz = p.v * p.oz;
     const int nb = p.n_bins;
     const int ka = p.kbin;  // bin_of(ca): the end bin of the previous segment
-    if constexpr (FORM == FORM_PERSISTENT) {
+    if constexpr (FORM != FORM_PLAIN) {
         bin_add<R, FORM, G>(p, a, sh, ka, seg, vz, true);
         // the position update of the step computes exactly cb, so kb is the next
         // segment's start bin (a boundary interaction recomputes it); a flight
@@ -1203,7 +1209,7 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
         if (interact(p, J, surf, w)) return 1;
         if (G == GEOM_SLAB || p.n_bins > 0) {
             set_kbin(p);  // a periodic face moves the particle to the other end
-            if (FORM == FORM_PERSISTENT) bin_enter<R, FORM, G>(p, a, sh, p.kbin);
+            if (FORM != FORM_PLAIN) bin_enter<R, FORM, G>(p, a, sh, p.kbin);
         }
     } else {                                                          // step IVb
         const uint32_t m = alias_draw(sh.gain, a.gain_bits, w.y);
@@ -1363,6 +1369,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const Shared sh = setup_shared<R, FORM_PERSISTENT>(a, smem);
+    constexpr int PF = BOUNDED ? FORM_EPOCH : FORM_PERSISTENT;
     const int lane = (int)(threadIdx.x & 63);
     Lane<R> p;
     bool alive = false;
@@ -1388,7 +1395,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
         const bool have_work = pool_left > 0u || !qdry;
         if (n_free > 0 && have_work && (n_free >= a.refill_min || n_free == 64)) {
             if (ended) {
-                finish<R, FORM_PERSISTENT, G>(p, a, sh, a.jobs[p.job], ended == 2);
+                finish<R, PF, G>(p, a, sh, a.jobs[p.job], ended == 2);
                 ended = 0;
             }
             while (need) {
@@ -1440,10 +1447,10 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
             // started, to the next launch
             if (++drain > a.drain_iters) {
                 if (ended) {
-                    finish<R, FORM_PERSISTENT, G>(p, a, sh, a.jobs[p.job], ended == 2);
+                    finish<R, PF, G>(p, a, sh, a.jobs[p.job], ended == 2);
                     ended = 0;
                 }
-                if (alive) suspend<R, FORM_PERSISTENT, G>(p, a, sh);
+                if (alive) suspend<R, PF, G>(p, a, sh);
                 alive = false;
                 while (pool_left > 0u) {
                     const uint32_t avail = pool_left;
@@ -1456,7 +1463,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                             job = find_job(a, q - (uint64_t)a.n_resume, job);
                             emit<R, G>(p, a, sh, a.jobs[job], q, job);
                         }
-                        suspend<R, FORM_PERSISTENT, G>(p, a, sh);
+                        suspend<R, PF, G>(p, a, sh);
                     }
                     const uint32_t n = (avail < 64u) ? avail : 64u;
                     pool_cur += n;
@@ -1483,22 +1490,22 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
         }
         if (alive) {
             const JobDev &J = a.jobs[p.job];
-            const int r = step<R, FORM_PERSISTENT, G>(p, a, sh, J, wk);
+            const int r = step<R, PF, G>(p, a, sh, J, wk);
             if (r != 0) {
                 if (DEFER_FINISH)
                     ended = r;
                 else
-                    finish<R, FORM_PERSISTENT, G>(p, a, sh, J, r == 2);
+                    finish<R, PF, G>(p, a, sh, J, r == 2);
                 alive = false;
             }
         }
-        if (defer_snapshots<R, FORM_PERSISTENT, G>()) {
+        if (defer_snapshots<R, PF, G>()) {
             // score the recorded crossings together once a quarter of the wave has one
             if (__popcll(__ballot(alive && p.pend >= 0)) >= 16 && alive && p.pend >= 0)
                 snapshot_commit(p, a, a.jobs[p.job]);
         }
     }
-    if (ended) finish<R, FORM_PERSISTENT, G>(p, a, sh, a.jobs[p.job], ended == 2);
+    if (ended) finish<R, PF, G>(p, a, sh, a.jobs[p.job], ended == 2);
     flush_shared(a, sh);
 }
 
@@ -1557,7 +1564,7 @@ template <typename R, int G>
 const void *kernel_ptr(int form, bool bounded)
 {
     if (form == FORM_PLAIN) return (const void *)plain_kernel<R, G>;
-    return bounded ? (const void *)persistent_kernel<R, GEOM_ANY, true> : (const void *)persistent_kernel<R, G, false>;
+    return bounded ? (const void *)persistent_kernel<R, G, true> : (const void *)persistent_kernel<R, G, false>;
 }
 
 template <typename R>

@@ -6,6 +6,8 @@
 // range, so a request that arrives while others run joins at the next epoch
 // and its particles share the device with theirs.  Slices are sized so each
 // admitted request receives an equal share of the epoch's estimated flights.
+// With class epochs, an epoch takes only the requests of one class (the classes
+// take turns), so it runs that class's specialised kernel.
 // Particles are independent and their random numbers are keyed by (seed, pid),
 // so a request's realisation does not depend on how it was sliced or with
 // which other requests it ran.
@@ -72,8 +74,25 @@ private:
     std::map<size_t, size_t> free_, used_;
 };
 
+// Epoch classes: the kernel specialisation a request runs in when an epoch
+// holds only its class (wall-driven slabs, transient half spaces, gradient
+// films and pore cells, others).  Without class epochs every request is in
+// group 0.
+constexpr int kClasses = 4;
+
+int class_of(const JobHost &h)
+{
+    switch (kernel_spec(&h.dev, 1)) {
+    case GEOM_SLAB: return 0;
+    case GEOM_HALF: return 1;
+    case GEOM_GRAD: return 2;
+    default: return 3;
+    }
+}
+
 struct Request {
     uint64_t ticket = 0;
+    int cls = 3;              // epoch class
     JobHost jh;
     size_t bytes = 0, arena_off = 0;
     uint64_t cursor = 0;      // next pid not yet emitted
@@ -101,16 +120,19 @@ struct dmc_server {
     uint64_t next_ticket = 1;
     std::vector<JobDev> epoch_table;  // upload sources of the running epoch
     std::vector<double> epoch_times;
-    // particles suspended at the end of the previous epoch (double-buffered)
-    Suspended *susp[2] = {nullptr, nullptr};
+    // Suspended particles wait per epoch group (one group per class with class
+    // epochs, else a single group) until their group's next epoch, which resumes them from the
+    // group's buffer and suspends into the spare one; the two then swap.
+    Suspended *rest[kClasses] = {nullptr, nullptr, nullptr, nullptr};
+    Suspended *spare = nullptr;
     uint32_t susp_cap = 0;
-    int cur = 0;                     // buffer holding the previous epoch's suspended particles
-    uint32_t n_susp = 0;
-    // last epoch's members and how many particles each left suspended; a member
-    // with none may have finished and been collected since, so its pointer is
-    // never followed
-    std::vector<Request *> prev_members;
-    std::vector<uint64_t> prev_suspended;
+    uint32_t n_rest[kClasses] = {0, 0, 0, 0};
+    // each group's last epoch: its members and how many particles each left
+    // suspended; a member with none may have finished and been collected since,
+    // so its pointer is never followed
+    std::vector<Request *> prev_members[kClasses];
+    std::vector<uint64_t> prev_suspended[kClasses];
+    int next_class = 0;              // round-robin start of the class choice
     int32_t *d_resume_job = nullptr;
     std::vector<int32_t> h_resume_job;
     dmc_stats totals{};              // all epochs so far
@@ -120,8 +142,9 @@ struct dmc_server {
         if (ev1) (void)hipEventDestroy(ev1);
         if (arena_mem) (void)hipFree(arena_mem);
         if (scratch) (void)hipFree(scratch);
-        for (Suspended *p : susp)
+        for (Suspended *p : rest)
             if (p) (void)hipFree(p);
+        if (spare) (void)hipFree(spare);
         if (d_resume_job) (void)hipFree(d_resume_job);
     }
 };
@@ -181,11 +204,11 @@ extern "C" dmc_status dmc_server_create(const dmc_material *material, const dmc_
     // each lane of an epoch may suspend its particle and each wave up to one
     // chunk (<= 64) of unstarted indices: twice the resident lanes
     S->susp_cap = (uint32_t)cus * 4096u;
-    for (int i = 0; i < 2; ++i)
-        if (hipMalloc(&S->susp[i], (size_t)S->susp_cap * sizeof(Suspended)) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(DMC_E_NOMEM, "cannot allocate the suspended-particle buffers");
-        }
+    if (hipMalloc(&S->spare, (size_t)S->susp_cap * sizeof(Suspended)) != hipSuccess) {
+        (void)hipGetLastError();
+        S->spare = nullptr;
+        return fail(DMC_E_NOMEM, "cannot allocate the suspended-particle buffers");
+    }
     if (hipMalloc(&S->d_resume_job, (size_t)nj * sizeof(int32_t)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(DMC_E_NOMEM, "cannot allocate server scratch");
@@ -209,6 +232,7 @@ extern "C" dmc_status dmc_server_submit(dmc_server *S, const dmc_job *job, uint6
     r->bytes = a256((size_t)std::max<int64_t>(r->jh.size, 1) * sizeof(double));
     if (r->bytes > S->opts.memory_budget) return fail(DMC_E_INVALID, "request can never fit the memory budget");
     r->flights_per_particle = flights_estimate(*S->M, r->jh);
+    r->cls = S->opts.class_epochs ? class_of(r->jh) : 0;  // without class epochs: a single group
     std::lock_guard<std::mutex> g(S->mu);
     r->ticket = S->next_ticket++;
     *ticket = r->ticket;
@@ -226,6 +250,14 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
     times.clear();
     std::vector<Request *> members;
     LaunchBuffers lb = S->sb;
+    int cls = 0;
+    if (!S->spare) {  // the buffer the coming epoch suspends into
+        if (hipMalloc(&S->spare, (size_t)S->susp_cap * sizeof(Suspended)) != hipSuccess) {
+            (void)hipGetLastError();
+            S->spare = nullptr;
+            return fail(DMC_E_NOMEM, "cannot allocate a suspended-particle buffer");
+        }
+    }
     {
         std::lock_guard<std::mutex> g(S->mu);
         // admit in arrival order while a slot and memory are free
@@ -239,11 +271,26 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
             S->pending.pop_front();
         }
         if (S->active.empty()) return DMC_OK;
+        // the epoch's group: the next class, in turn, with admitted requests
+        // (always group 0 without class epochs)
+        bool has[kClasses] = {false, false, false, false};
+        for (auto &rp : S->active) has[rp->cls] = true;
+        for (int k = 0; k < kClasses; ++k) {
+            const int c = (S->next_class + k) % kClasses;
+            if (has[c]) {
+                cls = c;
+                break;
+            }
+        }
+        S->next_class = (cls + 1) % kClasses;
+        size_t n_members = 0;
+        for (auto &rp : S->active) n_members += (rp->cls == cls) ? 1 : 0;
         const double epoch_flights = S->opts.epoch_flights ? (double)S->opts.epoch_flights : 2.0e10;
-        const double share = epoch_flights / (double)S->active.size();
+        const double share = epoch_flights / (double)n_members;
         uint64_t base = 0;
         for (auto &rp : S->active) {
             Request *r = rp.get();
+            if (r->cls != cls) continue;
             const uint64_t left = r->jh.dev.n - r->cursor;
             uint64_t n = (uint64_t)std::max(256.0, share / r->flights_per_particle);
             n = std::min(n, left);
@@ -270,11 +317,12 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
         // particles suspended last epoch resume first; their slots map to this
         // epoch's job table (jobs are queued in member order, so index = member)
         S->h_resume_job.assign((size_t)S->opts.max_active, 0);
-        for (size_t i = 0; i < S->prev_members.size(); ++i) {
-            if (S->prev_suspended[i] == 0) continue;  // no particle of this slot resumes
+        const std::vector<Request *> &pm = S->prev_members[cls];
+        for (size_t i = 0; i < pm.size(); ++i) {
+            if (S->prev_suspended[cls][i] == 0) continue;  // no particle of this slot resumes
             int32_t idx = -1;
             for (size_t j = 0; j < members.size(); ++j)
-                if (members[j] == S->prev_members[i]) idx = (int32_t)j;
+                if (members[j] == pm[i]) idx = (int32_t)j;
             if (idx < 0) return fail(DMC_E_DEVICE, "internal: a request with suspended particles left the epoch");
             S->h_resume_job[i] = idx;
         }
@@ -287,10 +335,10 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
     for (size_t i = 0; i < members.size(); ++i) fresh = fresh || devs[i].n > 0;
     const uint32_t drain = S->opts.drain_flights ? S->opts.drain_flights : 2048u;
     lb.drain_iters = fresh ? drain : 16u * drain;
-    lb.n_resume = S->n_susp;
-    lb.resume_in = S->susp[S->cur];
+    lb.n_resume = S->n_rest[cls];
+    lb.resume_in = S->rest[cls];  // NULL only while the group has never suspended (n_resume = 0)
     lb.resume_job = S->d_resume_job;
-    lb.suspend_out = S->susp[1 - S->cur];
+    lb.suspend_out = S->spare;
     lb.suspend_cap = S->susp_cap;
     dmc_status st = enqueue_launch(S->M, devs, times, S->epoch_table, lb, 0, false, S->opts.run, s, S->ev0, S->ev1);
     if (st != DMC_OK) return st;
@@ -310,7 +358,7 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
         r->kernel_ms += ms;
         r->cursor += devs[i].n;
     }
-    S->n_susp = (uint32_t)n_susp;
+    S->n_rest[cls] = (uint32_t)n_susp;
     for (size_t i = 0; i < members.size(); ++i) {
         S->totals.particles += stats[i * kStats + 0];
         S->totals.scatters += stats[i * kStats + 1];
@@ -319,10 +367,10 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
         S->totals.capped += stats[i * kStats + 4];
     }
     S->totals.kernel_ms += ms;
-    S->cur = 1 - S->cur;
-    S->prev_members = members;
-    S->prev_suspended.resize(members.size());
-    for (size_t i = 0; i < members.size(); ++i) S->prev_suspended[i] = members[i]->suspended;
+    std::swap(S->rest[cls], S->spare);  // the group's particles now wait in what was the spare
+    S->prev_members[cls] = members;
+    S->prev_suspended[cls].resize(members.size());
+    for (size_t i = 0; i < members.size(); ++i) S->prev_suspended[cls][i] = members[i]->suspended;
     for (size_t i = 0; i < S->active.size();) {
         Request *r = S->active[i].get();
         if (r->cursor >= r->jh.dev.n && r->suspended == 0) {

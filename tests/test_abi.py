@@ -52,7 +52,7 @@ def layout_probe(tmp_path_factory):
         "dmc_job": ["material", "geometry", "source", "tally", "n_particles", "seed", "times", "n_times",
                     "first_particle"],
         "dmc_stats": ["particles", "scatters", "boundary", "iterations", "capped", "kernel_ms"],
-        "dmc_server_opts": ["memory_budget", "max_active", "epoch_flights", "drain_flights", "run"],
+        "dmc_server_opts": ["memory_budget", "max_active", "epoch_flights", "drain_flights", "class_epochs", "run"],
         "dmc_trunc_opts": ["n_pilot", "k_pilot", "bias_fraction"],
         "dmc_trunc_plan": ["kmax", "k_uncertain", "fit_ok", "n_fit", "decay", "amplitude", "bias_bound", "kappa_se",
                            "kappa_pilot", "n_pilot"],

@@ -29,13 +29,17 @@ def _requests(si):
     ]
 
 
-def test_mix_equals_alone_and_requests_join_running_epochs():
+@pytest.mark.parametrize("class_epochs", [False, True])
+def test_mix_equals_alone_and_requests_join_running_epochs(class_epochs):
+    """Mixed epochs (every request, the generic kernel) and class epochs (each
+    epoch one class of requests in its specialised kernel, the other classes'
+    suspended particles waiting) both give every request its solo result."""
     si = di.silicon_like()
     mat = b.Material(si)
     reqs = _requests(si)
     # a small epoch budget slices every request over several epochs; a small memory
     # budget and 3 slots force queueing and admission as memory frees up
-    srv = b.Server(mat, memory_budget=4 << 20, max_active=3, epoch_flights=1e6)
+    srv = b.Server(mat, memory_budget=4 << 20, max_active=3, epoch_flights=1e6, class_epochs=class_epochs)
     tickets = [srv.submit(j) for j in reqs[:3]]
     srv.step()
     q, r = srv.load()
@@ -128,4 +132,40 @@ def test_results_collected_between_epochs():
             solo.close()
     assert steps >= 4
     assert srv.load() == (0, 0)
+    srv.close()
+
+
+@pytest.mark.parametrize("kind", ["slab", "pore", "spot"])
+def test_single_class_epochs_match_oracle(kind):
+    """Epochs whose requests are all of one class run that class's specialised
+    kernel in its time-bounded form; FP64 epochs that suspend particles after 16
+    flights reproduce the FP64 oracle (same realisation)."""
+    import oracle
+    from gpu_cases import compare_sections, lib_sections, vmax_of
+
+    si = di.silicon_like()
+    mat = b.Material(si)
+    jobs = {
+        "slab": [di.slab_job(si, 1e-6, 2_000, seed=2201, n_bins=20), di.slab_job(si, 3e-7, 3_000, seed=2202, n_bins=10)],
+        "pore": [di.pore_cell(100e-9, 0.3, 3_000, seed=2203, material=si, kmax=40, n_hj=10),
+                 di.in_plane_film(60e-9, 0.5, 3_000, seed=2204, material=si, kmax=40, n_hj=4)],
+        "spot": [small_spot(n=1_500, seed=2205, grid=8, n_times=5, mat=si),
+                 small_spot(n=1_000, seed=2206, grid=8, n_times=4, mat=si)],
+    }[kind]
+    srv = b.Server(mat, memory_budget=16 << 20, max_active=4, epoch_flights=2e3, drain_flights=16, precision="fp64")
+    tickets = [srv.submit(j) for j in jobs]
+    steps = 0
+    while not all(srv.done(t) for t in tickets):
+        srv.step()
+        steps += 1
+        assert steps < 100_000
+    assert steps > 5  # every request was sliced over several epochs
+    for t, job in zip(tickets, jobs):
+        res = srv.collect(t)
+        prep = oracle.prepare(job)
+        oraw, ocnt, _ = oracle.run_raw(job, threads=16, prep=prep)
+        worst, ok = compare_sections(lib_sections(job, res.raw(0)), oracle.split_raw(prep, oraw), 1e-9, vmax_of(job))
+        assert ok, (job.name, worst)
+        st = res.stats(0)
+        assert st.particles == job.n_particles and st.scatters == ocnt["scatters"], job.name
     srv.close()
