@@ -56,7 +56,7 @@ OPS_PER_FLIGHT = 100
 # WRITE_SIZE runs (profiles/), scaled by the same counters' reading for a plain
 # device copy of known size (bench.py --copy-probe); valid only for the kernel
 # source it was measured on.
-TRAFFIC = {"kernel_sha1": "b3fcb229ce8c46623a615a61fce554994dfccbc7", "bytes": 54557246}  # profiles/persistent_kernel_slab_12films_counters.md
+TRAFFIC = {"kernel_sha1": "b965e223def12ead7bb4a044bcaed0f127e8f72d", "bytes": 54548576}  # profiles/persistent_kernel_slab_12films_counters.md
 CU, LANES_PER_CU_CLK, CLOCK = 256, 64, 2.4e9
 PEAK_LANE_OPS = CU * LANES_PER_CU_CLK * CLOCK  # 3.93e13 full-rate VALU lane-ops/s
 
