@@ -163,9 +163,12 @@ struct Pr<double> {
 template <>
 struct Pr<float> {
     static constexpr float inf() { return __builtin_huge_valf(); }
-    // ((w >> 9) + 1/2) 2^-23 as one FMA: 24 significant bits, so exact; strictly
-    // inside (0, 1), never denormal
-    __device__ static float u(uint32_t w) { return fmaf((float)(w >> 9), 1.1920928955078125e-07f, 5.9604644775390625e-08f); }
+    // ((w >> 9) + 1/2) 2^-23, strictly inside (0, 1), never denormal.  One funnel
+    // shift puts the top 23 bits of w under the exponent of 1.0 (a = 1 + (w >> 9)
+    // 2^-23, in [1, 2)); subtracting 1 - 2^-24 is exact (the difference has 24
+    // significant bits).
+    __device__ static float one_plus(uint32_t w) { return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9u)); }
+    __device__ static float u(uint32_t w) { return one_plus(w) - 0x1.fffffep-1f; }
     // -tau ln u with the hardware log2 (u >= 2^-24, so no range fix-ups are needed)
     __device__ static float flight(float ntl, uint32_t w) { return ntl * __builtin_amdgcn_logf(u(w)); }
     __device__ static float sq(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -179,8 +182,8 @@ struct Pr<float> {
     __device__ static float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     __device__ static float ptime(float t, float, float itau) { return t * itau; }
     __device__ static float lg(float x) { return __builtin_amdgcn_logf(x) * 0.693147182f; }
-    // 2u - 1 is exact for these u, so one FMA gives the same value
-    __device__ static float mu(uint32_t w) { return fmaf(2.0f, u(w), -1.0f); }
+    // 2u - 1 = (2a - 3) + 2^-23 with a = 1 + (w >> 9) 2^-23: both steps exact
+    __device__ static float mu(uint32_t w) { return fmaf(one_plus(w), 2.0f, -3.0f) + 0x1p-23f; }
     // a position rounded just past a wall must not yield a negative flight time
     __device__ static float nonneg(float t) { return fmaxf(t, 0.0f); }
 };
