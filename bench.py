@@ -34,12 +34,13 @@ sys.path.insert(0, ROOT)
 # Algorithmic VALU work of one flight of the cross-plane slab path, counted in
 # full-rate VALU issue slots per lane (the MI355X issues 64 lane-slots per CU
 # per clock).  Instruction costs on gfx950 were measured with a throughput
-# probe: a Philox4x32-10 block (20 32x32->64 multiply-adds and the xors, with
-# the key schedule on the scalar unit since a wave's particles share a seed)
-# takes 57 lane-slots; v_log_f32 takes 2.
-#   Philox4x32-10 block                                                  57
-#   two word -> uniform conversions (shift, convert, one FMA each)          6
-#   flight time (-tau ln2) log2 u: log2 (2), one multiply; mu = 2u - 1      4
+# probe: a Philox4x32-10 block (20 32x32->64 multiply-adds and 20 three-input
+# xors, with the key schedule on the scalar unit since a wave's particles share
+# a seed) takes 43 lane-slots; v_log_f32 takes 2.
+#   Philox4x32-10 block                                                  43
+#   uniform u for the flight (funnel shift, subtract)                      2
+#   mu = 2u - 1 from a second word (funnel shift, FMA, add)                3
+#   flight time (-tau ln2) log2 u: log2 (2), one multiply                  3
 #   wall distance and reciprocal, hit test, segment select                 8
 #   position update                                                        2
 #   end-of-segment bin index (scale, floor, convert, 2 clamps), compare     6
@@ -51,12 +52,12 @@ sys.path.insert(0, ROOT)
 # start bin of a segment is the end bin of the previous one, so one bin index
 # per flight is the minimum; the signed length through a bin depends only on a
 # trajectory's end points, so it costs nothing per flight.
-OPS_PER_FLIGHT = 100
+OPS_PER_FLIGHT = 84
 # HBM traffic of one launch of the timed workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs (profiles/), scaled by the same counters' reading for a plain
 # device copy of known size (bench.py --copy-probe); valid only for the kernel
 # source it was measured on.
-TRAFFIC = {"kernel_sha1": "b965e223def12ead7bb4a044bcaed0f127e8f72d", "bytes": 54548576}  # profiles/persistent_kernel_slab_12films_counters.md
+TRAFFIC = {"kernel_sha1": "a3f7d45e0037d965770ed7264b5cfeee99a95e00", "bytes": 54558304}  # profiles/persistent_kernel_slab_12films_counters.md
 CU, LANES_PER_CU_CLK, CLOCK = 256, 64, 2.4e9
 PEAK_LANE_OPS = CU * LANES_PER_CU_CLK * CLOCK  # 3.93e13 full-rate VALU lane-ops/s
 

@@ -1392,9 +1392,11 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
     bool qdry = false;  // the global queue has handed out every index (wave-uniform)
     uint32_t drain = 0, poll = 0, iter = 0;
     WaveKey wk{0u, 0u, false};
+    const uint64_t wave_lanes = __ballot(true);
     for (;;) {
         // refill free lanes from this wave's chunk, taking a new chunk from the
-        // queue (one atomic per wave) when it is used up
+        // queue (one atomic per wave) when it is used up; need stays the mask of
+        // the free lanes through the refill
         uint64_t need = __ballot(!alive);
         const int n_free = __popcll(need);
         const bool have_work = pool_left > 0u || !qdry;
@@ -1445,7 +1447,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
             const unsigned long long head = __hip_atomic_load(a.queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (head >= a.total) qdry = true;
         }
-        if (__ballot(alive) == 0ull && !(pool_left > 0u || !qdry)) break;
+        if (need == wave_lanes && !(pool_left > 0u || !qdry)) break;  // no lane is live
         if (BOUNDED && qdry) {
             // time-bounded launch: the queue is dry; a fixed number of flights later
             // this wave hands its live particles, and any indices of its chunk not yet
