@@ -204,6 +204,8 @@ struct Lane {
     // cached job parameters
     int32_t geom, src, n_bins, n_hj, kmax, n_times;
     R len, bpl, bw;
+    R rad2;  // pore radius squared (pore cells); kept in a register so the boundary
+             // search of every flight does not wait on a load of the job descriptor
     uint32_t key0, key1;
     // tally addresses of this particle: bins of its batch (LDS index or, if
     // bl < 0, HBM offset) and the H_j block
@@ -343,6 +345,7 @@ __device__ __forceinline__ void bind_job(Lane<R> &p, const JobDev &J, uint64_t p
     p.kmax = (G == GEOM_SLAB) ? -1 : J.kmax;
     p.n_times = (G == GEOM_SLAB || G == GEOM_GRAD) ? 0 : J.n_times;
     p.len = (R)J.length;
+    p.rad2 = (R)J.radius * (R)J.radius;
     p.bpl = (R)J.bins_per_len;
     p.bw = (R)J.bin_width;
     p.key0 = J.key0;
@@ -435,7 +438,7 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
             p.x = p.len * Pr<R>::u(B.x);
         } else {
             const R c = (R)0.5 * p.len;
-            const R r2 = (R)J.radius * (R)J.radius;
+            const R r2 = p.rad2;
             bool ok = false;
             for (uint32_t att = 0; att < (uint32_t)kPosAttempts && !ok; ++att) {
                 const uint4 Bb = (att == 0) ? B : philox(plo, phi, att, TAG_EMIT_B, p.key0, p.key1);
@@ -920,13 +923,13 @@ __device__ __forceinline__ R search(const Lane<R> &p, const JobDev &J, int geom,
                 surf = id;
             }
         }
-        const R rad = (R)J.radius;
-        if (rad > (R)0 && p.last != 4) {
+        const R r2 = p.rad2;
+        if (r2 > (R)0 && p.last != 4) {
             const R c = (R)0.5 * p.len;
             const R dx = p.x - c, dz = p.z - c;
             const R aq = p.ox * p.ox + p.oz * p.oz;
             const R bq = dx * p.ox + dz * p.oz;
-            const R cq = dx * dx + dz * dz - rad * rad;
+            const R cq = dx * dx + dz * dz - r2;
             if (aq > (R)0 && bq < (R)0) {
                 R dist = Pr<R>::inf();
                 if (cq <= (R)0)
