@@ -14,8 +14,9 @@ Layers:
     E_eff / T) and the conversion of raw sums into temperatures, heat fluxes,
     conductivities and standard errors.
 
-parity unpinned: the pore-cell geometry (no closed form or printed value
-exists; it is checked only through its bulk limit and invariants).
+The pore-cell geometry has no printed value; it is pinned by brute-force ray
+marching of the boundary search, the area law of the emitted positions and
+Cauchy's mean chord formula for a ballistic walk (tests/test_oracle_pins.py).
 """
 from __future__ import annotations
 
@@ -108,6 +109,12 @@ def lib():
             L.oracle_log.argtypes = [C.c_double]
             L.oracle_log.restype = C.c_double
             L.oracle_sincos2pi.argtypes = [C.c_double, f64p, f64p]
+            L.oracle_boundary_search.argtypes = [C.POINTER(Problem), f64p, f64p, C.c_double, C.c_int32,
+                                                 C.POINTER(C.c_int32)]
+            L.oracle_boundary_search.restype = C.c_double
+            L.oracle_emit.argtypes = [C.POINTER(Problem), C.c_uint64, f64p, f64p, u32p, f64p]
+            L.oracle_pore_chords.argtypes = [C.POINTER(Problem), C.c_uint64, C.c_uint64, C.c_uint32, f64p, f64p]
+            L.oracle_pore_chords.restype = C.c_uint64
             _lib = L
     return _lib
 
@@ -309,6 +316,38 @@ def prepare(job: di.Job) -> Prepared:
         P.region_z[0], P.region_z[1] = float(rg[3]), float(rg[4])
     size = int(lib().oracle_tally_size(C.byref(P)))
     return Prepared(job, P, keep, C_tot, G_tau, G_v, power, steady, avg_volume, size)
+
+
+def boundary_search(prep: "Prepared", x, o, v: float = 1.0, last: int = -1):
+    """Step III for one state: (hit time, surface index); surface -1 and an
+    infinite time when the ray meets no surface."""
+    xa = np.ascontiguousarray(x, dtype=np.float64)
+    oa = np.ascontiguousarray(o, dtype=np.float64)
+    surf = C.c_int32(0)
+    t = lib().oracle_boundary_search(C.byref(prep.struct), _p(xa, C.c_double), _p(oa, C.c_double), float(v),
+                                     int(last), C.byref(surf))
+    return float(t), int(surf.value)
+
+
+def emit_state(prep: "Prepared", pid: int):
+    """Step I for one particle id: (position, direction, state, sign)."""
+    x = np.zeros(3)
+    o = np.zeros(3)
+    m = C.c_uint32(0)
+    s = C.c_double(0.0)
+    lib().oracle_emit(C.byref(prep.struct), int(pid), _p(x, C.c_double), _p(o, C.c_double), C.byref(m), C.byref(s))
+    return x, o, int(m.value), float(s.value)
+
+
+def pore_chords(prep: "Prepared", pid_begin: int, pid_end: int, n_chords: int):
+    """Ballistic walk in a pore cell (see oracle_pore_chords): (number of chords
+    between consecutive pore hits, sum of their lengths, sum of their x-z
+    projections)."""
+    s3 = C.c_double(0.0)
+    s2 = C.c_double(0.0)
+    n = lib().oracle_pore_chords(C.byref(prep.struct), int(pid_begin), int(pid_end), int(n_chords), C.byref(s3),
+                                 C.byref(s2))
+    return int(n), float(s3.value), float(s2.value)
 
 
 # --------------------------------------------------------------------------

@@ -798,6 +798,84 @@ int oracle_run(const oracle_problem *P, uint64_t pid0, uint64_t pid1, double *ta
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Geometry hooks for the tests                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Step III for one given state: the surface hit time along x + v Omega t and
+ * the surface index (pore cell: 0 x=0, 1 x=P, 2 z=0, 3 z=P, 4 pore). */
+double oracle_boundary_search(const oracle_problem *P, const double x[3], const double o[3], double v,
+                              int32_t last, int32_t *surf)
+{
+    particle p;
+    memset(&p, 0, sizeof(p));
+    for (int i = 0; i < 3; ++i) { p.x[i] = x[i]; p.o[i] = o[i]; }
+    p.last = last;
+    return boundary_search(P, &p, v, surf);
+}
+
+/* Step I for one particle id: position, direction, state and sign. */
+void oracle_emit(const oracle_problem *P, uint64_t pid, double x[3], double o[3], uint32_t *m, double *s)
+{
+    particle p;
+    emit(P, pid, &p);
+    for (int i = 0; i < 3; ++i) { x[i] = p.x[i]; o[i] = p.o[i]; }
+    *m = p.m;
+    *s = p.s;
+}
+
+/* Ballistic walk in a pore cell (no scattering): each particle of [pid0, pid1)
+ * is emitted, then moved from surface to surface with the same search, wrap
+ * and pore interaction as oracle_run (pore words from the STEP blocks, one
+ * block per interaction), until it has completed n_chords chords between
+ * consecutive pore hits.  Sums the chord lengths (unwrapped, 3-D) and their
+ * projections on the x-z plane; a walk whose ray meets no surface (parallel to
+ * the pore axis) ends early.  Returns the number of chords. */
+uint64_t oracle_pore_chords(const oracle_problem *P, uint64_t pid0, uint64_t pid1, uint32_t n_chords,
+                            double *sum_len, double *sum_len_xz)
+{
+    uint64_t done = 0;
+    double s3 = 0.0, s2 = 0.0;
+    oracle_counters cnt;
+    memset(&cnt, 0, sizeof(cnt));
+    if (P->geom != OR_GEOM_PORE_XZ) return 0;
+    for (uint64_t pid = pid0; pid < pid1; ++pid) {
+        particle p;
+        emit(P, pid, &p);
+        uint32_t k = 0, chords = 0;
+        int started = 0;
+        double len = 0.0;
+        while (chords < n_chords && k < OR_ITER_CAP) {
+            int32_t surf;
+            double t = boundary_search(P, &p, 1.0, &surf);
+            if (!isfinite(t)) break;
+            for (int i = 0; i < 3; ++i) p.x[i] += p.o[i] * t;
+            len += t;
+            uint32_t w[4];
+            rng_block(P->seed, pid, k, OR_TAG_STEP, w);
+            ++k;
+            if (surf < 4) {
+                int ax = (surf < 2) ? 0 : 2;
+                p.x[ax] = (surf % 2 == 1) ? P->length : 0.0;
+            } else {
+                if (started) {
+                    double sxz = sqrt(p.o[0] * p.o[0] + p.o[2] * p.o[2]);
+                    s3 += len;
+                    s2 += len * sxz;
+                    ++chords;
+                    ++done;
+                }
+                started = 1;
+                len = 0.0;
+            }
+            wall_interaction(P, &p, surf, w, &cnt);
+        }
+    }
+    *sum_len = s3;
+    *sum_len_xz = s2;
+    return done;
+}
+
 /* Raw Philox words for one (seed, pid, k, tag), exported for the tests. */
 void oracle_rng_block(uint64_t seed, uint64_t pid, uint32_t k, uint32_t tag, uint32_t out[4])
 {

@@ -539,3 +539,118 @@ def test_field_symmetries_of_the_pore_cell():
     # the temperature field is resolved: odd in z with a clear sign on the lower and upper halves
     lower, upper = T[:6][ok[:6]].mean(), T[6:][ok[6:]].mean()
     assert lower * upper < 0
+
+
+# --------------------------------------------------------------------------
+# Pore-cell geometry (the periodic nanostructure of the conductivity section):
+# step III against brute-force ray marching, step I's positions against the
+# area of the solid, and the chords between pore hits against Cauchy's mean
+# chord formula for cosine-law re-emission.
+# --------------------------------------------------------------------------
+
+
+def _pore_prep(porosity, period=100e-9, specularity=0.0, n=1000, seed=41):
+    job = di.pore_cell(period, porosity, n, seed, material=di.gray_material(), kmax=40, n_hj=0,
+                       specularity=specularity)
+    return job, oracle.prepare(job)
+
+
+def _in_solid(x, z, P, r, tol):
+    c = 0.5 * P
+    return (x >= -tol) & (x <= P + tol) & (z >= -tol) & (z <= P + tol) & \
+        (np.hypot(x - c, z - c) >= r * (1.0 - 1e-12) - tol)
+
+
+@pytest.mark.parametrize("porosity", [0.05, 0.3, 0.6])
+def test_pore_boundary_search_against_ray_marching(porosity):
+    """The first surface the oracle reports is where the ray leaves the solid:
+    the hit point lies on the reported face or on the pore, the ray moves into
+    that surface there, and 400 points marched along the ray before it are all
+    inside the solid of the cell."""
+    job, prep = _pore_prep(porosity)
+    P, r, c = job.geometry.length, job.geometry.radius, 0.5 * job.geometry.length
+    rng = np.random.default_rng(7)
+    tol = 1e-12 * P
+    frac = np.linspace(1e-6, 1.0 - 1e-6, 400)
+    seen = set()
+    for _ in range(1500):
+        while True:
+            x0, z0 = rng.uniform(0.0, P, 2)
+            if math.hypot(x0 - c, z0 - c) > r:
+                break
+        mu = rng.uniform(-1.0, 1.0)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        st = math.sqrt(1.0 - mu * mu)
+        o = np.array([st * math.cos(ph), st * math.sin(ph), mu])
+        x = np.array([x0, rng.uniform(-P, P), z0])
+        t, surf = oracle.boundary_search(prep, x, o, v=1.0)
+        assert np.isfinite(t) and t >= 0.0 and surf in (0, 1, 2, 3, 4)
+        seen.add(surf)
+        h = x + o * t
+        if surf == 4:
+            assert abs(math.hypot(h[0] - c, h[2] - c) - r) <= 1e-9 * r
+            assert (h[0] - c) * o[0] + (h[2] - c) * o[2] < 0.0  # entering the pore
+        else:
+            ax = 0 if surf < 2 else 2
+            edge = P if surf % 2 == 1 else 0.0
+            assert abs(h[ax] - edge) <= 1e-9 * P
+            assert (o[ax] > 0.0) == (surf % 2 == 1)  # leaving through that face
+        pts = x[None, :] + (t * frac)[:, None] * o[None, :]
+        assert np.all(_in_solid(pts[:, 0], pts[:, 2], P, r, tol)), (x, o, t, surf)
+    assert seen == {0, 1, 2, 3, 4}
+
+
+def test_pore_search_excludes_the_resting_surface():
+    """A particle resting on a face or on the pore is not found to hit it again
+    at distance zero (the exclusion rule of the boundary search)."""
+    job, prep = _pore_prep(0.3)
+    P, r, c = job.geometry.length, job.geometry.radius, 0.5 * job.geometry.length
+    # on the pore, leaving it outward along the normal: the next hit is a face
+    n = np.array([1.0, 0.0, 1.0]) / math.sqrt(2.0)
+    x = np.array([c + r * n[0], 0.0, c + r * n[2]])
+    t, surf = oracle.boundary_search(prep, x, n, v=1.0, last=4)
+    assert surf in (1, 3) and abs(t - (P - (c + r * n[0])) / n[0]) <= 1e-12 * P
+    # on the face x = 0, moving in +x: the next hit is the pore or x = P, never face 0
+    x = np.array([0.0, 0.0, 0.1 * P])
+    t, surf = oracle.boundary_search(prep, x, np.array([1.0, 0.0, 0.0]), v=1.0, last=0)
+    assert surf == 1 and abs(t - P) <= 1e-12 * P
+
+
+def test_pore_emission_is_uniform_in_the_solid():
+    """The gradient source places particles uniformly in the solid of the cell:
+    the fraction within distance rho of the pore axis is the annulus area over
+    the solid area, and the mean position is the cell centre."""
+    job, prep = _pore_prep(0.3, n=30_000)
+    P, r, c = job.geometry.length, job.geometry.radius, 0.5 * job.geometry.length
+    xs = np.array([oracle.emit_state(prep, pid)[0] for pid in range(job.n_particles)])
+    n = len(xs)
+    rho = np.hypot(xs[:, 0] - c, xs[:, 2] - c)
+    assert np.all(rho >= r) and np.all((xs[:, [0, 2]] >= 0.0) & (xs[:, [0, 2]] <= P))
+    solid = P * P - math.pi * r * r
+    for rho0 in (1.2 * r, 0.4 * P, 0.5 * P):
+        p = (math.pi * rho0 * rho0 - math.pi * r * r) / solid
+        f = np.mean(rho < rho0)
+        assert abs(f - p) <= 4.0 * math.sqrt(p * (1.0 - p) / n), (rho0, f, p)
+    for ax in (0, 2):
+        sd = P / math.sqrt(12.0)  # at most the spread of a uniform variable on [0, P]
+        assert abs(xs[:, ax].mean() - c) <= 4.0 * sd / math.sqrt(n)
+
+
+@pytest.mark.parametrize("porosity", [0.1, 0.3, 0.5])
+def test_pore_mean_chord_is_cauchys(porosity):
+    """Ballistic walk with diffuse (cosine-law) pore walls: the mean path length
+    between consecutive pore hits is 4 V / S of the solid (Cauchy's formula; per
+    unit length along the pore axis V = P^2 - pi r^2, S = 2 pi r), and its
+    projection on the x-z plane has the two-dimensional mean pi A / perimeter.
+    Chord lengths are heavy-tailed (rays nearly parallel to the axis or to an
+    open channel), so the tolerance is 3 %."""
+    job, prep = _pore_prep(porosity, n=20_000)
+    P, r = job.geometry.length, job.geometry.radius
+    n, s3, s2 = oracle.pore_chords(prep, 0, job.n_particles, 40)
+    assert n > 0.95 * 40 * job.n_particles
+    mean3, mean2 = s3 / n, s2 / n
+    solid = P * P - math.pi * r * r
+    ref3 = 4.0 * solid / (2.0 * math.pi * r)
+    ref2 = math.pi * solid / (2.0 * math.pi * r)
+    assert abs(mean3 / ref3 - 1.0) < 0.03, (mean3, ref3)
+    assert abs(mean2 / ref2 - 1.0) < 0.03, (mean2, ref2)
