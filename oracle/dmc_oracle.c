@@ -734,13 +734,26 @@ int oracle_run(const oracle_problem *P, uint64_t pid0, uint64_t pid1, double *ta
             memset(rq, 0, (size_t)P->n_times * sizeof(double));
         }
         cnt->particles++;
+        /* A free flight that reaches a periodic face continues from the opposite
+         * face with the time it has left (rem >= 0), using the words of the block
+         * drawn when it began; any other event ends it and the next flight draws
+         * a new block.  One loop iteration is one segment. */
+        uint32_t w[4];
+        double rem = -1.0;
+        uint32_t nseg = 0;
         for (;;) {
-            uint32_t w[4];
-            rng_block(P->seed, pid, k, OR_TAG_STEP, w);
-            ++k;
-            cnt->iterations++;
             double v = P->v[p.m], tau_m = P->tau[p.m];
-            double dt = -tau_m * oracle_log(unif(w[0]));               /* step II */
+            double dt;
+            if (rem < 0.0) {
+                rng_block(P->seed, pid, k, OR_TAG_STEP, w);
+                ++k;
+                dt = -tau_m * oracle_log(unif(w[0]));                    /* step II */
+            } else {
+                dt = rem;
+            }
+            rem = -1.0;
+            ++nseg;
+            cnt->iterations++;
             int32_t surf;
             double tb = boundary_search(P, &p, v, &surf);             /* step III */
             int boundary = (tb <= dt);
@@ -763,7 +776,10 @@ int oracle_run(const oracle_problem *P, uint64_t pid0, uint64_t pid1, double *ta
                 else if (P->geom == OR_GEOM_FILM_X) p.x[0] = (surf == 1) ? P->length : 0.0;
                 else if (surf < 4) { int ax = (surf < 2) ? 0 : 2; p.x[ax] = (surf % 2 == 1) ? P->length : 0.0; }
                 cnt->boundary++;
+                int periodic = (P->geom == OR_GEOM_PORE_XZ) ? (surf < 4)
+                             : (P->wall_type[(P->geom == OR_GEOM_HALFSPACE_Z) ? 0 : surf] == OR_WALL_PERIODIC);
                 if (wall_interaction(P, &p, surf, w, cnt)) { t = t_new; break; }
+                if (periodic) rem = dt - seg;
             } else {                                                  /* step IVb */
                 p.m = alias_draw(w[1], P->gain_bits, P->gain_thresh, P->gain_alias);
                 if (scatter_hist) scatter_hist[p.m] += 1;
@@ -775,7 +791,7 @@ int oracle_run(const oracle_problem *P, uint64_t pid0, uint64_t pid1, double *ta
                 if (P->first_event) { t = t_new; break; }              /* the first free path ends here */
             }
             t = t_new;
-            if (k >= OR_ITER_CAP) { cnt->capped++; break; }
+            if (nseg >= OR_ITER_CAP) { cnt->capped++; break; }
         }
         tally[lay.kappa + 0] += Lz;
         tally[lay.kappa + 1] += Lz * Lz;

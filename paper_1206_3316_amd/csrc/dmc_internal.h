@@ -76,7 +76,9 @@ struct alignas(16) Suspended {
     uint32_t k, nscat, nbound, m;
     int32_t last, tcur, slot, sign;
     double rt, rq;          // region tally sums of the current window
-    int32_t rwin, pad[3];
+    int32_t rwin;
+    uint32_t nseg;          // segments so far
+    double rem;             // free-flight time left after a periodic face (< 0: none)
 };
 static_assert(sizeof(Suspended) == 144, "Suspended layout");
 

@@ -199,6 +199,8 @@ struct Lane {
     R s;                    // sign
     int32_t last;           // surface the particle rests on (excluded from the next search)
     uint32_t k, nscat, nbound;
+    uint32_t nseg;          // segments so far (kernels with periodic faces; elsewhere every segment is a flight)
+    R rem;                  // free-flight time left after a periodic face (< 0: none)
     uint64_t pid;
     int32_t job, batch, slot;
     // cached job parameters
@@ -384,6 +386,8 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
     p.x = p.y = p.z = (R)0;
     p.last = kNoSurface;
     p.k = 0;
+    p.nseg = 0;
+    p.rem = (R)-1;
     p.nscat = 0;
     p.nbound = 0;
     p.t = 0.0;
@@ -472,6 +476,21 @@ __device__ __forceinline__ void bins_add(const Lane<R> &p, const KArgs &a, const
         atomicAdd(sh.ltally + (p.bl + idx), v);
     else
         tadd(a, sh, p.bl, p.bg, idx, v);
+}
+
+// Kernels whose geometries have periodic faces (pore cells, films with periodic
+// walls); elsewhere every segment is a whole free flight.
+template <int G>
+__device__ constexpr bool has_periodic()
+{
+    return G == GEOM_GRAD || G == GEOM_ANY;
+}
+
+// Segments a particle has run (what the flight cap and the age-graded priority count).
+template <typename R, int G>
+__device__ __forceinline__ uint32_t segments(const Lane<R> &p)
+{
+    return has_periodic<G>() ? p.nseg : p.k;
 }
 
 // Deferred snapshot scoring: FP32 persistent half-space kernel.
@@ -949,9 +968,12 @@ __device__ __forceinline__ R search(const Lane<R> &p, const JobDev &J, int geom,
     return Pr<R>::nonneg(best);
 }
 
-// Step IVa.  Returns true if the particle is absorbed.
+enum { HIT_REFLECTED = 0, HIT_ABSORBED = 1, HIT_PERIODIC = 2 };
+
+// Step IVa.  Returns HIT_ABSORBED if the particle ends, HIT_PERIODIC if it was
+// moved to the opposite periodic face, HIT_REFLECTED otherwise.
 template <typename R>
-__device__ bool interact(Lane<R> &p, const JobDev &J, int32_t surf, const uint4 &w)
+__device__ int interact(Lane<R> &p, const JobDev &J, int32_t surf, const uint4 &w)
 {
     if (p.geom == GEOM_PORE) {
         if (surf < 4) {
@@ -962,7 +984,7 @@ __device__ bool interact(Lane<R> &p, const JobDev &J, int32_t surf, const uint4 
             else
                 p.z = v;
             p.last = (surf % 2 == 1) ? surf - 1 : surf + 1;
-            return false;
+            return HIT_PERIODIC;
         }
         const R c = (R)0.5 * p.len;
         const R nx = p.x - c, nz = p.z - c;
@@ -982,12 +1004,12 @@ __device__ bool interact(Lane<R> &p, const JobDev &J, int32_t surf, const uint4 
             p.oz = mu * n2 + st * (s3 * n0);
         }
         p.last = 4;
-        return false;
+        return HIT_REFLECTED;
     }
     const int wall = (p.geom == GEOM_HALF) ? 0 : surf;
     const int ax = (p.geom == GEOM_FILM) ? 0 : 2;
     const int32_t type = J.wall_type[wall];
-    if (type == WALL_ISOTHERMAL) return true;
+    if (type == WALL_ISOTHERMAL) return HIT_ABSORBED;
     if (type == WALL_PERIODIC) {
         const R v = (wall == 1) ? (R)0 : p.len;
         if (ax == 2)
@@ -995,7 +1017,7 @@ __device__ bool interact(Lane<R> &p, const JobDev &J, int32_t surf, const uint4 
         else
             p.x = v;
         p.last = (wall == 1) ? 0 : 1;
-        return false;
+        return HIT_PERIODIC;
     }
     if ((uint64_t)w.y < J.spec_thr[wall]) {
         if (ax == 2)
@@ -1003,11 +1025,11 @@ __device__ bool interact(Lane<R> &p, const JobDev &J, int32_t surf, const uint4 
         else
             p.ox = -p.ox;
     } else {
-        if (J.first_event) return true;  // a diffuse reflection ends the first free path
+        if (J.first_event) return HIT_ABSORBED;  // a diffuse reflection ends the first free path
         lambertian_plane(p, ax, wall == 0 ? (R)1 : (R)-1, w.z, w.w);
     }
     p.last = wall;
-    return false;
+    return HIT_REFLECTED;
 }
 
 // ------------------------------------------------------- suspend / resume ----
@@ -1029,6 +1051,9 @@ __device__ void suspend(Lane<R> &p, const KArgs &a, const Shared &sh)
     S.h = p.h;
     S.pid = p.pid;
     S.k = p.k;
+    // kernels without periodic faces: every segment is a flight and none is pending
+    S.nseg = has_periodic<G>() ? p.nseg : p.k;
+    S.rem = has_periodic<G>() ? (double)p.rem : -1.0;
     S.nscat = p.nscat;
     S.nbound = p.nbound;
     S.m = p.m;
@@ -1062,6 +1087,10 @@ __device__ void resume(Lane<R> &p, const KArgs &a, const Shared &sh, uint32_t i)
     p.Lz = S.Lz;
     p.h = S.h;
     p.k = S.k;
+    if (has_periodic<G>()) {
+        p.nseg = S.nseg;
+        p.rem = (R)S.rem;
+    }
     p.nscat = S.nscat;
     p.nbound = S.nbound;
     p.last = S.last;
@@ -1108,7 +1137,7 @@ __device__ void finish(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDe
         tadd(a, sh, p.hl, p.hg, p.n_hj + (int32_t)p.nscat, p.h * p.h);
     }
     if (a.nscat_out) a.nscat_out[J.out_off + (p.pid - J.pid0)] = p.nscat;
-    const unsigned long long vals[kStats] = {1ull, p.nscat, p.nbound, p.k, capped ? 1ull : 0ull};
+    const unsigned long long vals[kStats] = {1ull, p.nscat, p.nbound, segments<R, G>(p), capped ? 1ull : 0ull};
     if (a.lds_stats) {
 #pragma unroll
         for (int i = 0; i < kStats; ++i)
@@ -1158,82 +1187,107 @@ __device__ __forceinline__ WaveKey wave_key_active(const Lane<R> &p)
 
 // The STEP block of flight k.
 template <typename R>
-__device__ __forceinline__ uint4 philox_step(const Lane<R> &p, const WaveKey &wk)
+__device__ __forceinline__ uint4 philox_step(const Lane<R> &p, const WaveKey &wk, uint32_t k)
 {
     const uint32_t c0 = (uint32_t)p.pid, c1 = (uint32_t)(p.pid >> 32);
-    if (wk.uniform) return philox(c0, c1, p.k, TAG_STEP, wk.k0, wk.k1);
-    return philox(c0, c1, p.k, TAG_STEP, p.key0, p.key1);
+    if (wk.uniform) return philox(c0, c1, k, TAG_STEP, wk.k0, wk.k1);
+    return philox(c0, c1, k, TAG_STEP, p.key0, p.key1);
 }
 
+
 // One iteration of steps II-VI.  Returns 0 if the particle goes on, 1 if it
-// ended, 2 if it hit the flight cap.
+// ended, 2 if it hit the flight cap.  A free flight that reaches a periodic face
+// continues from the opposite face with the time it has left and the words of
+// the block drawn when it began; in the gradient kernel such a continuation runs
+// in the same call for up to `hops` segments (waves with few live lanes pass a
+// large budget, so a lone long flight does not pay a whole iteration per face),
+// else in the next.
 template <typename R, int FORM, int G>
-__device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, const WaveKey &wk)
+__device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, const WaveKey &wk,
+                                    uint32_t hops)
 {
-    const uint4 w = philox_step(p, wk);
-    ++p.k;
-    const R dt = Pr<R>::flight(sizeof(R) == 4 ? p.ntl : p.tau, w.x);  // step II
-    int32_t surf;
+    constexpr bool PER = has_periodic<G>();
+    const bool cont = PER && p.rem >= (R)0;
+    const uint4 w = philox_step(p, wk, cont ? p.k - 1u : p.k);
+    R dt;
+    if (cont) {
+        dt = p.rem;
+    } else {
+        ++p.k;
+        dt = Pr<R>::flight(sizeof(R) == 4 ? p.ntl : p.tau, w.x);  // step II
+    }
     const int geom = (G == GEOM_ANY || G == GEOM_GRAD) ? p.geom : G;
-    const R tb = search(p, J, geom, surf);                           // step III
-    const bool boundary = (tb <= dt);
-    const R seg = boundary ? tb : dt;
-    // step V: sample the segment
-    if (G == GEOM_SLAB || p.n_bins > 0) score_bins<R, FORM, G>(p, a, sh, J, seg);  // the slab kernel always has bins
-    if constexpr (G == GEOM_GRAD || G == GEOM_ANY) {
-        if (p.fld) score_field(p, a, sh, J, seg);
-    }
     const bool gradient = (G == GEOM_GRAD) || ((G == GEOM_ANY) && (p.src == SRC_GRADIENT));
-    if (gradient) {
-        const double dz = (double)(p.s * p.v * p.oz * seg);
-        p.Lz += dz;
-        if (p.nscat < (uint32_t)p.n_hj) p.h += dz;
-    }
-    if (G == GEOM_ANY || G == GEOM_HALF) {
-        const double tb_abs = p.t + (double)seg;
-        if (p.tnext < tb_abs) score_snapshots<R, defer_snapshots<R, FORM, G>()>(p, a, J, (double)seg);
-        // windowed region tally; most segments lie wholly above the region
-        if (fmin(p.z, p.z + p.v * p.oz * seg) < p.rzhi) score_region(p, a, sh, J, seg);
-        if (tb_abs > p.tend) return 1;  // step VI
-    }
-    // move
-    p.x += p.v * p.ox * seg;
-    p.y += p.v * p.oy * seg;
-    p.z += p.v * p.oz * seg;
-    p.t += (double)seg;
-    if (boundary) {                                                   // step IVa
-        if (geom == GEOM_SLAB || geom == GEOM_HALF)
-            p.z = (surf == 1) ? p.len : (R)0;
-        else if (geom == GEOM_FILM)
-            p.x = (surf == 1) ? p.len : (R)0;
-        else if (surf < 4) {
-            const R v = (surf % 2 == 1) ? p.len : (R)0;
-            if (surf < 2)
-                p.x = v;
-            else
-                p.z = v;
+    for (uint32_t hop = 1;; ++hop) {
+        if (PER) {
+            p.rem = (R)-1;
+            ++p.nseg;
         }
-        ++p.nbound;
-        if (interact(p, J, surf, w)) return 1;
-        if (G == GEOM_SLAB || p.n_bins > 0) {
-            set_kbin(p);  // a periodic face moves the particle to the other end
-            if (FORM != FORM_PLAIN) bin_enter<R, FORM, G>(p, a, sh, p.kbin);
+        int32_t surf;
+        const R tb = search(p, J, geom, surf);                           // step III
+        const bool boundary = (tb <= dt);
+        const R seg = boundary ? tb : dt;
+        // step V: sample the segment
+        if (G == GEOM_SLAB || p.n_bins > 0) score_bins<R, FORM, G>(p, a, sh, J, seg);  // the slab kernel always has bins
+        if constexpr (G == GEOM_GRAD || G == GEOM_ANY) {
+            if (p.fld) score_field(p, a, sh, J, seg);
         }
-    } else {                                                          // step IVb
-        const uint32_t m = alias_draw(sh.gain, a.gain_bits, w.y);
-        load_state(p, a, sh, m);
-        isotropic(p, w.z, w.w);
-        p.last = kNoSurface;
-        if (gradient && p.nscat < (uint32_t)p.n_hj) {
-            tadd(a, sh, p.hl, p.hg, (int32_t)p.nscat, p.h);
-            tadd(a, sh, p.hl, p.hg, p.n_hj + (int32_t)p.nscat, p.h * p.h);
-            p.h = 0.0;
+        if (gradient) {
+            const double dz = (double)(p.s * p.v * p.oz * seg);
+            p.Lz += dz;
+            if (p.nscat < (uint32_t)p.n_hj) p.h += dz;
         }
-        ++p.nscat;
-        if (p.kmax >= 0 && p.nscat >= (uint32_t)p.kmax) return 1;
+        if (G == GEOM_ANY || G == GEOM_HALF) {
+            const double tb_abs = p.t + (double)seg;
+            if (p.tnext < tb_abs) score_snapshots<R, defer_snapshots<R, FORM, G>()>(p, a, J, (double)seg);
+            // windowed region tally; most segments lie wholly above the region
+            if (fmin(p.z, p.z + p.v * p.oz * seg) < p.rzhi) score_region(p, a, sh, J, seg);
+            if (tb_abs > p.tend) return 1;  // step VI
+        }
+        // move
+        p.x += p.v * p.ox * seg;
+        p.y += p.v * p.oy * seg;
+        p.z += p.v * p.oz * seg;
+        p.t += (double)seg;
+        if (boundary) {                                                   // step IVa
+            if (geom == GEOM_SLAB || geom == GEOM_HALF)
+                p.z = (surf == 1) ? p.len : (R)0;
+            else if (geom == GEOM_FILM)
+                p.x = (surf == 1) ? p.len : (R)0;
+            else if (surf < 4) {
+                const R v = (surf % 2 == 1) ? p.len : (R)0;
+                if (surf < 2)
+                    p.x = v;
+                else
+                    p.z = v;
+            }
+            ++p.nbound;
+            const int hit = interact(p, J, surf, w);
+            if (hit == HIT_ABSORBED) return 1;
+            if (G == GEOM_SLAB || p.n_bins > 0) {
+                set_kbin(p);  // a periodic face moves the particle to the other end
+                if (FORM != FORM_PLAIN) bin_enter<R, FORM, G>(p, a, sh, p.kbin);
+            }
+            if (PER && hit == HIT_PERIODIC) p.rem = dt - seg;
+        } else {                                                          // step IVb
+            const uint32_t m = alias_draw(sh.gain, a.gain_bits, w.y);
+            load_state(p, a, sh, m);
+            isotropic(p, w.z, w.w);
+            p.last = kNoSurface;
+            if (gradient && p.nscat < (uint32_t)p.n_hj) {
+                tadd(a, sh, p.hl, p.hg, (int32_t)p.nscat, p.h);
+                tadd(a, sh, p.hl, p.hg, p.n_hj + (int32_t)p.nscat, p.h * p.h);
+                p.h = 0.0;
+            }
+            ++p.nscat;
+            if (p.kmax >= 0 && p.nscat >= (uint32_t)p.kmax) return 1;
+        }
+        if (segments<R, G>(p) >= a.iter_cap) return 2;
+        // the generic kernel continues in the next iteration (registers are
+        // scarcer there)
+        if (!(G == GEOM_GRAD && p.rem >= (R)0 && hop < hops)) return 0;
+        dt = p.rem;
     }
-    if (p.k >= a.iter_cap) return 2;
-    return 0;
 }
 
 __device__ __forceinline__ int find_job(const KArgs &a, uint64_t q, int hint)
@@ -1354,7 +1408,7 @@ __global__ void __launch_bounds__(256) plain_kernel(KArgs a)
         emit<R, G>(p, a, sh, J, q, job);
         int r;
         do {
-            r = step<R, FORM_PLAIN, G>(p, a, sh, J, wave_key_active(p));
+            r = step<R, FORM_PLAIN, G>(p, a, sh, J, wave_key_active(p), 1u);
         } while (r == 0);
         finish<R, FORM_PLAIN, G>(p, a, sh, J, r == 2);
     }
@@ -1394,6 +1448,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
     uint32_t pool_left = 0;
     bool qdry = false;  // the global queue has handed out every index (wave-uniform)
     uint32_t drain = 0, poll = 0, iter = 0;
+    uint32_t old_hops = 1;  // periodic-face budget of a wave holding a long-running particle
     WaveKey wk{0u, 0u, false};
     const uint64_t wave_lanes = __ballot(true);
     for (;;) {
@@ -1489,18 +1544,32 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
             // (past prio_flights, 4x and 16x that), so the longest-running
             // trajectories advance first; their other lanes keep refilling as usual
             const uint32_t t1 = a.prio_flights;
-            if (__ballot(alive && p.k >= 16u * t1))
+            const uint32_t age = segments<R, G>(p);
+            if (__ballot(alive && age >= 16u * t1))
                 __builtin_amdgcn_s_setprio(3);
-            else if (__ballot(alive && p.k >= 4u * t1))
+            else if (__ballot(alive && age >= 4u * t1))
                 __builtin_amdgcn_s_setprio(2);
-            else if (__ballot(alive && p.k >= t1))
+            else if (__ballot(alive && age >= t1))
                 __builtin_amdgcn_s_setprio(1);
             else
                 __builtin_amdgcn_s_setprio(0);
+            if constexpr (G == GEOM_GRAD) {
+                // a wave holding a long-running particle also lets its flights
+                // cross several periodic faces per iteration (4 from t1 / 16
+                // segments on, 16 from t1, 64 from 16 t1), so the longest
+                // trajectories do not pace the launch
+                old_hops = __ballot(alive && age >= 16u * t1) ? 64u
+                         : __ballot(alive && age >= t1) ? 16u
+                         : __ballot(alive && age >= t1 / 16u) ? 4u : 1u;
+            }
         }
+        // a wave down to a few live lanes (the tail of a launch) lets a flight
+        // cross up to 64 periodic faces per iteration; a wave holding a
+        // long-running particle, the budget graded by its age
+        const uint32_t hops = (G == GEOM_GRAD && __popcll(wave_lanes & ~need) <= 4) ? 64u : old_hops;
         if (alive) {
             const JobDev &J = a.jobs[p.job];
-            const int r = step<R, PF, G>(p, a, sh, J, wk);
+            const int r = step<R, PF, G>(p, a, sh, J, wk, hops);
             if (r != 0) {
                 if (DEFER_FINISH)
                     ended = r;
