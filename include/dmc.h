@@ -343,7 +343,7 @@ typedef struct {
     uint64_t particles;  /* particles completed */
     uint64_t scatters;   /* scattering events (step IVb only) */
     uint64_t boundary;   /* boundary interactions (step IVa) */
-    uint64_t iterations; /* flights (Philox STEP blocks) */
+    uint64_t iterations; /* trajectory segments (one per free flight, plus one per periodic face crossed) */
     uint64_t capped;     /* particles stopped by the 2^24-flight safety cap */
     double kernel_ms;    /* device time of the trajectory launch(es), HIP events */
 } dmc_stats;

@@ -111,7 +111,7 @@ struct KArgs {
     const int32_t *resume_job;      // device-table job of each resumed particle's slot
     Suspended *suspend_out;
     uint32_t suspend_cap;
-    uint32_t iter_cap;              // flights after which a particle is stopped and counted as capped
+    uint32_t iter_cap;              // segments after which a particle is stopped and counted as capped
     uint32_t prio_flights;          // persistent: waves holding a particle past this many flights (4x,
                                     // 16x) get SIMD issue priority 1 (2, 3); 0: off; at most 2^27
 };
