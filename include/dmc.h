@@ -190,11 +190,13 @@ typedef struct {
     uint32_t *nscat_out;   /* optional device array (sum of the jobs' n_particles entries): the
                               scattering events of particle pid of job j are written at
                               (n_particles of jobs 0..j-1) + pid; not used by the server */
-    int32_t prio_flights;  /* persistent: a wave holding a particle past this many flights
+    int32_t prio_flights;  /* persistent: a wave holding a particle past this many segments
                               (4x, 16x as many) gets issue priority 1 (2, 3) on its SIMD,
                               so that the few longest trajectories of a heavy-tailed job
-                              do not end the launch late; 0 = 65536, < 0 = off, at most
-                              2^27.  Changes timing only. */
+                              do not end the launch late; in the gradient kernel such a
+                              wave also lets a flight cross up to 4 (16, 64) periodic faces
+                              per iteration from 1/16 (1, 16) of this many segments on;
+                              0 = 65536, < 0 = off, at most 2^27.  Changes timing only. */
     int32_t pad0;
 } dmc_run_opts;
 
