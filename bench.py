@@ -57,7 +57,7 @@ OPS_PER_FLIGHT = 84
 # WRITE_SIZE runs (profiles/), scaled by the same counters' reading for a plain
 # device copy of known size (bench.py --copy-probe); valid only for the kernel
 # source it was measured on.
-TRAFFIC = {"kernel_sha1": "f5312c5bc1bdb1b26cca56f347548c6a1bc058b0", "bytes": 54552928}  # profiles/persistent_kernel_slab_12films_counters.md
+TRAFFIC = {"kernel_sha1": "beb9bf16be071456637116016faa292036a56a69", "bytes": 54553312}  # profiles/persistent_kernel_slab_12films_counters.md
 CU, LANES_PER_CU_CLK, CLOCK = 256, 64, 2.4e9
 PEAK_LANE_OPS = CU * LANES_PER_CU_CLK * CLOCK  # 3.93e13 full-rate VALU lane-ops/s
 

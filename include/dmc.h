@@ -194,7 +194,7 @@ typedef struct {
                               (4x, 16x as many) gets issue priority 1 (2, 3) on its SIMD,
                               so that the few longest trajectories of a heavy-tailed job
                               do not end the launch late; in the gradient kernel such a
-                              wave also lets a flight cross up to 4 (16, 64) periodic faces
+                              wave also lets a flight cross up to 8 (32, 64) periodic faces
                               per iteration from 1/16 (1, 16) of this many segments on;
                               0 = 65536, < 0 = off, at most 2^27.  Changes timing only. */
     int32_t pad0;

@@ -1555,12 +1555,12 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                 __builtin_amdgcn_s_setprio(0);
             if constexpr (G == GEOM_GRAD) {
                 // a wave holding a long-running particle also lets its flights
-                // cross several periodic faces per iteration (4 from t1 / 16
-                // segments on, 16 from t1, 64 from 16 t1), so the longest
+                // cross several periodic faces per iteration (8 from t1 / 16
+                // segments on, 32 from t1, 64 from 16 t1), so the longest
                 // trajectories do not pace the launch
                 old_hops = __ballot(alive && age >= 16u * t1) ? 64u
-                         : __ballot(alive && age >= t1) ? 16u
-                         : __ballot(alive && age >= t1 / 16u) ? 4u : 1u;
+                         : __ballot(alive && age >= t1) ? 32u
+                         : __ballot(alive && age >= t1 / 16u) ? 8u : 1u;
             }
         }
         // a wave down to a few live lanes (the tail of a launch) lets a flight
