@@ -31,28 +31,104 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic VALU work of one flight of the cross-plane slab path, counted in
-# full-rate VALU issue slots per lane (the MI355X issues 64 lane-slots per CU
-# per clock).  Instruction costs on gfx950 were measured with a throughput
-# probe: a Philox4x32-10 block (20 32x32->64 multiply-adds and 20 three-input
-# xors, with the key schedule on the scalar unit since a wave's particles share
-# a seed) takes 43 lane-slots; v_log_f32 takes 2.
-#   Philox4x32-10 block                                                  43
-#   uniform u for the flight (funnel shift, subtract)                      2
-#   mu = 2u - 1 from a second word (funnel shift, FMA, add)                3
-#   flight time (-tau ln2) log2 u: log2 (2), one multiply                  3
-#   wall distance and reciprocal, hit test, segment select                 8
-#   position update                                                        2
-#   end-of-segment bin index (scale, floor, convert, 2 clamps), compare     6
-#   two FP64 tally accumulations, time and time/tau (1 FP32 product,
-#   2 converts, 2 adds; the particle's sign multiplies the sums once)      5
-#   gain alias draw (shift, mask, compare, select) + state fetch address    6
-#   flight / scatter counters and the flight-cap test                       4
-# plus 2 for the sign and select logic of the boundary/scatter outcome.  The
-# start bin of a segment is the end bin of the previous one, so one bin index
-# per flight is the minimum; the signed length through a bin depends only on a
-# trajectory's end points, so it costs nothing per flight.
-OPS_PER_FLIGHT = 84
+# Algorithmic VALU work, counted in full-rate VALU issue slots per lane (the
+# MI355X issues 64 lane-slots per CU per clock).  The costs of the operations
+# that are not one slot each (a Philox4x32-10 block: 20 32x32->64 multiply-adds
+# and 20 three-input xors, with the key schedule on the scalar unit since a
+# wave's particles share a seed; the transcendental and reciprocal
+# instructions; FP64 adds) are measured live by the library's instruction-cost
+# probe (dmc_debug_op_cost, op_costs() below; figures in profiles/op_costs.md).
+# Every other item is one full-rate instruction per slot.  The counts are the
+# cheapest form of each step found so far: a kernel change that removes work
+# from the minimum lowers them, so the fraction does not flatter an older,
+# costlier kernel.
+def slab_items(c):
+    """One flight of the cross-plane slab path (persistent FP32 slab kernel).
+    The start bin of a segment is the end bin of the previous one, so one bin
+    index per flight is the minimum; the signed length through a bin depends
+    only on a trajectory's end points, so it costs nothing per flight; a slab
+    needs only the z direction cosine after a scattering event (no azimuth)."""
+    return [
+        ("Philox4x32-10 block", c["philox_uniform_key"]),
+        ("uniform u for the flight (funnel shift, subtract)", 2),
+        ("mu = 2u - 1 from a second word (funnel shift, FMA, add)", 3),
+        ("flight time -tau ln2 log2 u: log2, one multiply", c["log"] + 1),
+        ("wall distance through the reciprocal of the axial speed, hit test, segment select", 7 + c["rcp"]),
+        ("position update", 2),
+        ("end-of-segment bin index (scale, truncate, 2 clamps), compare with the start bin", 6),
+        ("two FP64 tally sums, time and time/tau (1 FP32 product, 2 converts, 2 adds)", 3 + 2 * c["f64_add"]),
+        ("gain alias draw (shift, mask, compare, select) + state fetch address", 6),
+        ("flight / scatter counters and the flight-cap test", 4),
+        ("sign and select logic of the boundary / scatter outcome", 2),
+    ]
+
+
+def half_items(c):
+    """One flight of the transient half-space path (heated spot, snapshot
+    estimator only): nearly every flight ends in a scattering event (the surface
+    is met on few flights), and a snapshot crossing (50 per particle over about
+    2744 flights) costs a cell index (3 axes: subtract, scale, floor, convert, 2
+    compares) and one FP64 atomic, about 25 slots, i.e. 0.46 per flight."""
+    return [
+        ("Philox4x32-10 block", c["philox_uniform_key"]),
+        ("flight time: uniform (2), log2, one multiply", 3 + c["log"]),
+        ("surface distance through the reciprocal of v Omega_z, hit test, select", 4 + c["rcp"]),
+        ("segment end time t + seg in FP64 (convert, add), next-sample and final-time compares",
+         3 + c["f64_add"]),
+        ("position update (v seg, 3 FMAs)", 4),
+        ("gain alias draw + state fetch address", 6),
+        ("isotropic direction: mu (3), azimuth uniform (2), sin, cos, sqrt(1 - mu^2) (1 + sqrt), 2 products",
+         8 + c["sin"] + c["cos"] + c["sqrt"]),
+        ("flight / scatter counters and the flight-cap test", 3),
+        ("outcome select", 2),
+        ("snapshot crossings, amortised", 0.46),
+    ]
+
+
+def grad_unit_costs(c):
+    """Per-event algorithmic costs of the in-plane film and pore-cell path under
+    the gradient source (GEOM_GRAD kernel): a flight draws one Philox block; each
+    segment searches the surfaces and adds its algebraic z length (and H_j);
+    segments end in a scattering event, a wall or pore-surface interaction, or a
+    periodic face crossing (the flight continues with its remaining time)."""
+    search_film = 5 + c["rcp"]  # one candidate plane by the sign of the axial speed
+    # two periodic face pairs (each: speed, sign tests, distance through the reciprocal) and
+    # the pore's quadratic: offsets (2), a, b, c (7), discriminant (2), sqrt, root through the
+    # reciprocal of a (2 + rcp), time through the reciprocal of v (1 + rcp), selects (4)
+    search_pore = 2 * (5 + c["rcp"]) + 18 + c["sqrt"] + 2 * c["rcp"]
+    seg_common = (2  # outcome compare, select
+                  + 4  # position update
+                  + 3 + 2 * c["f64_add"]  # s v Omega_z seg to FP64, added to L_z and H_j
+                  + 3)  # segment counter, cap test, continuation test
+    return {
+        "flight": c["philox_uniform_key"] + 3 + c["log"],
+        "segment_film": search_film + seg_common,
+        "segment_pore": search_pore + seg_common,
+        "scatter": 6 + 8 + c["sin"] + c["cos"] + c["sqrt"] + 1 + 2 * c["f64_add"],  # alias, isotropic, H_j flush
+        # specular test (2) + Lambertian about the wall normal: mu = sqrt(u) (2 + sqrt), azimuth
+        # (2 + sin + cos), sqrt(1 - mu^2) (1 + sqrt), 3 components
+        "wall_hit": 10 + 2 * c["sqrt"] + c["sin"] + c["cos"],
+        # the pore normal (2 offsets, norm: 2 + sqrt, 2 products through its reciprocal) and the
+        # cosine law about it in the tangent frame (6 components)
+        "pore_hit": 8 + c["sqrt"] + c["rcp"] + 2 + 3 + 2 * c["sqrt"] + c["sin"] + c["cos"] + 6,
+        "periodic": 4,  # wrap the coordinate, remaining time, resting face
+    }
+
+
+OP_COST_ITERS = {"fma": 200_000, "philox_uniform_key": 4_000, "philox_lane_key": 3_000, "log": 60_000,
+                 "sin": 60_000, "cos": 60_000, "sqrt": 60_000, "rcp": 60_000, "f64_add": 100_000}
+
+
+def op_costs(b):
+    """VALU issue slots per lane of each operation the counts use, from the
+    library's instruction-cost probe at full occupancy."""
+    out = {}
+    for op, iters in OP_COST_ITERS.items():
+        ms, n = b.debug_op_cost(op, iters)
+        out[op] = ms * 1e-3 * PEAK_LANE_OPS / n
+    return out
+
+
 # HBM traffic of one launch of the timed workload from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs (profiles/), scaled by the same counters' reading for a plain
 # device copy of known size (bench.py --copy-probe); valid only for the kernel
@@ -96,7 +172,23 @@ def cpu_baseline(jobs, target_s=15.0):
     n1, ev1, dt1 = grow(1, target_s / 3)  # one core, for the per-core rate
     return {"value": ev / dt, "unit": "scattering events/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} particles of each of the 12 films ({ev} scattering events, {dt:.1f} s)",
+            "cpu": host_cpu(),
             "single_core": {"value": ev1 / dt1, "sample": f"first {n1} particles of each film ({ev1} events, {dt1:.1f} s)"}}
+
+
+def host_cpu():
+    """The host's processor model and logical CPU count (/proc/cpuinfo, os.cpu_count)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
 def launch_params(jobs, mat, precision="fp32", stream=None, overrides=None, tune=True):
@@ -117,15 +209,41 @@ def launch_params(jobs, mat, precision="fp32", stream=None, overrides=None, tune
     return params
 
 
-def other_workloads(b, di, mat, mat_in, stream):
+def grad_roofline(jobs, st, ms, costs):
+    """Algorithmic VALU work of a gradient-source launch (films and pore cells)
+    from its per-job event counts: flights (Philox blocks), segments, scattering
+    events, wall / pore-surface interactions and periodic face crossings
+    (segments - flights), each at its unit cost (grad_unit_costs)."""
+    u = grad_unit_costs(costs)
+    tot = {"flight": 0.0, "segment": 0.0, "scatter": 0.0, "hit": 0.0, "periodic": 0.0}
+    for j, s in zip(jobs, st):
+        pore = j.geometry.kind == "pore_cell_xz"
+        periodic = s.iterations - s.flights
+        hits = s.boundary - periodic
+        tot["flight"] += s.flights * u["flight"]
+        tot["segment"] += s.iterations * (u["segment_pore"] if pore else u["segment_film"])
+        tot["scatter"] += s.scatters * u["scatter"]
+        tot["hit"] += hits * (u["pore_hit"] if pore else u["wall_hit"])
+        tot["periodic"] += periodic * u["periodic"]
+    ops = sum(tot.values())
+    achieved = ops / (ms / 1e3)
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12, "unit": "T VALU lane-ops/s",
+            "frac": achieved / PEAK_LANE_OPS, "kernel": "persistent_kernel<float, GEOM_GRAD>",
+            "ops_per_launch": ops, "ops_by_event": {k: v for k, v in tot.items()},
+            "unit_costs_slots": {k: round(v, 3) for k, v in u.items()}}
+
+
+def other_workloads(b, di, mat, mat_in, stream, costs):
     """One autotuned launch each of the transient heated spot (1e9 particles,
-    64^3 grid x 50 times, and the windowed tally in a 10 um x 5 nm surface
-    cylinder like a thermoreflectance probe), of the 64 batched nanostructures (1e6-1e8 particles
-    each, K_max = 40), and of the same batch with first-event termination for
-    its 24 films (exact for films), after the tuner's trials have loaded the
-    kernels.  Reported beside the headline, not in it."""
+    64^3 grid x 50 times; alone, and with the windowed tally in a 10 um x 5 nm
+    surface cylinder like a thermoreflectance probe), of the 64 batched
+    nanostructures (1e6-1e8 particles each, K_max = 40), and of the same batch
+    with first-event termination for its 24 films (exact for films), after the
+    tuner's trials have loaded the kernels, each with the ALU roofline of its
+    kernel.  Reported beside the headline, not in it."""
     res = {}
-    for name, jobs in (("heated_spot_1e9_64cube_50times_ttr_probe",
+    for name, jobs in (("heated_spot_1e9_64cube_50times", [di.heated_spot(material=mat_in)]),
+                       ("heated_spot_1e9_64cube_50times_ttr_probe",
                         [di.heated_spot(material=mat_in, probe=di.TTR_PROBE)]),
                        ("nanostructures_64_instances", di.batched_nanostructures(material=mat_in)),
                        ("nanostructures_64_instances_first_event_films",
@@ -145,6 +263,18 @@ def other_workloads(b, di, mat, mat_in, stream):
         res[name] = {"scattering_events_per_s": sc / (ms / 1e3), "particles_per_s": parts / (ms / 1e3),
                      "flights_per_s": fl / (ms / 1e3), "kernel_ms": ms, "particles": parts, "scattering_events": sc,
                      "capped": sum(s.capped for s in st), "launch": params, "autotune_s": tune_s}
+        if name == "heated_spot_1e9_64cube_50times":
+            items = half_items(costs)
+            per = sum(v for _, v in items)
+            ach = per * fl / (ms / 1e3)
+            res[name]["roofline"] = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                                     "unit": "T VALU lane-ops/s", "frac": ach / PEAK_LANE_OPS,
+                                     "kernel": "persistent_kernel<float, GEOM_HALF>", "ops_per_flight": per,
+                                     "ops_items": [[k, round(v, 3)] for k, v in items]}
+        elif name.startswith("nanostructures"):
+            res[name]["roofline"] = grad_roofline(jobs, st, ms, costs)
+        if "roofline" in res[name]:
+            log(f"{name}: roofline fraction {res[name]['roofline']['frac']:.3f}")
         log(f"{name}: {sc:.3e} scatters in {ms:.1f} ms ({sc / (ms / 1e3):.3e} /s), params {params}")
         r.close()
     # the steady temperature and heat-flux fields of a pore cell (16 x 16 cells privatised in
@@ -186,6 +316,37 @@ def other_workloads(b, di, mat, mat_in, stream):
         f"{sc:.3e} scatters in {ms:.1f} ms (planning {plan_s:.1f} s)")
     r.close()
     return res
+
+
+def plain_vs_persistent(b, di, mat, mat_in, stream, n):
+    """The plain form (one FP64 launch per film, one thread per particle run to
+    completion, global tables, direct FP64 atomics) against the persistent
+    FP32-flight / FP64-tally batched form on the same 12 films at the same
+    particle count per film, i.e. at equal error (the persistent form in FP64 too,
+    to separate the precision from the form).  Kernel time from HIP events."""
+    pjobs = di.cross_plane_films(n_per_film=n, material=mat_in)
+    rp = b.simulate(pjobs, material=mat, precision="fp64", form="plain", stream=stream)
+    sp = rp.stats(-1)
+    rp.close()
+    log(f"plain form, {n:.0e} per film: {sp.scatters:.3e} scatters in {sp.kernel_ms:.1f} ms")
+    params = launch_params(pjobs, mat, stream=stream)
+    rq = b.simulate(pjobs, material=mat, precision="fp32", form="persistent", stream=stream, **params)
+    sq = rq.stats(-1)
+    rq.close()
+    p64 = launch_params(pjobs, mat, precision="fp64", stream=stream)
+    r64 = b.simulate(pjobs, material=mat, precision="fp64", form="persistent", stream=stream, **p64)
+    s64 = r64.stats(-1)
+    r64.close()
+    plain = sp.scatters / (sp.kernel_ms / 1e3)
+    pers = sq.scatters / (sq.kernel_ms / 1e3)
+    log(f"persistent, {n:.0e} per film: fp32 {sq.kernel_ms:.1f} ms, fp64 {s64.kernel_ms:.1f} ms; "
+        f"fp32 / plain = {pers / plain:.1f}")
+    return {"particles_per_film": n, "plain_fp64_events_per_s": plain, "plain_kernel_ms": sp.kernel_ms,
+            "persistent_fp32_events_per_s": pers, "persistent_fp32_kernel_ms": sq.kernel_ms,
+            "persistent_fp64_events_per_s": s64.scatters / (s64.kernel_ms / 1e3),
+            "persistent_fp64_kernel_ms": s64.kernel_ms, "persistent_fp32_over_plain": pers / plain,
+            "persistent_fp64_over_plain": (s64.scatters / (s64.kernel_ms / 1e3)) / plain,
+            "target_20x_met": bool(pers / plain >= 20.0), "launch_fp32": params, "launch_fp64": p64}
 
 
 def flights_per_particle(job, sums):
@@ -237,7 +398,7 @@ def serve(b, di, torch, mat, mat_in, stream, n_requests, args):
     budget = int(min(0.8 * free, 64 << 30))
     srv = b.Server(mat, budget, max_active=32, epoch_flights=args.epoch_flights, stream=stream, refill_min=4,
                    class_epochs=args.serve_class_epochs)
-    lat, kinds, scat = [], [], 0
+    lat, kinds, rel_se, kept, scat = [], [], [], {}, 0
     pending = {}
     i = 0
     epochs = 0
@@ -266,11 +427,9 @@ def serve(b, di, torch, mat, mat_in, stream, n_requests, args):
                 scat += res.stats(0).scatters
                 lat.append(t_done - ta)
                 kinds.append(reqs[k][0])
-                if k < 2:  # the same request alone must give the same result
-                    solo = b.simulate([reqs[k][1]], material=mat, stream=stream)
-                    a, c = res.raw(0), solo.raw(0)
-                    d = float(abs(a - c).max() / max(abs(c).max(), 1e-300))
-                    serve.mix_vs_alone = max(getattr(serve, "mix_vs_alone", 0.0), d)
+                rel_se.append(main_rel_se(b, res, reqs[k][0], reqs[k][1]))
+                if k % 20 == 0:  # kept for the comparison with the same request run alone
+                    kept[k] = res.raw(0)
                 res.close()
         elif i < n_requests:
             time.sleep(max(0.0, min(arrivals[i] - now, 0.05)))
@@ -281,13 +440,49 @@ def serve(b, di, torch, mat, mat_in, stream, n_requests, args):
                 f"events/s {scat / max(last_log, 1e-9):.3e}")
     wall = time.perf_counter() - t0
     srv.close()
-    lat_s = sorted(lat)
-    pct = lambda p: lat_s[min(len(lat_s) - 1, int(round(p / 100.0 * (len(lat_s) - 1))))]
-    return {"requests": n_requests, "arrival_rate_per_s": rate, "mix_capacity_flights_per_s": capacity, "p50_latency_s": pct(50), "p99_latency_s": pct(99),
+    # each kept request (every 20th) alone, after the stream: the same tallies as in the mix
+    worst = 0.0
+    for k, a in kept.items():
+        solo = b.simulate([reqs[k][1]], material=mat, stream=stream)
+        c = solo.raw(0)
+        worst = max(worst, float(abs(a - c).max() / max(abs(c).max(), 1e-300)))
+        solo.close()
+
+    def pct(vals, p):
+        v = sorted(vals)
+        return v[min(len(v) - 1, int(round(p / 100.0 * (len(v) - 1))))] if v else None
+
+    at = [l for l, e in zip(lat, rel_se) if e <= 1e-3]
+    by_kind = {}
+    for kd in sorted(set(kinds)):
+        e = [x for x, y in zip(rel_se, kinds) if y == kd]
+        by_kind[kd] = {"requests": len(e), "median_rel_se": pct(e, 50), "max_rel_se": max(e),
+                       "reached_1e-3": sum(1 for x in e if x <= 1e-3)}
+    return {"requests": n_requests, "arrival_rate_per_s": rate, "mix_capacity_flights_per_s": capacity,
+            "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99),
+            "requests_at_1e-3_rel_se": len(at), "p50_latency_at_1e-3_s": pct(at, 50),
+            "p99_latency_at_1e-3_s": pct(at, 99), "achieved_rel_se": by_kind,
+            "rel_se_quantity": {"film": "heat flux q", "pore": "kappa",
+                                "spot": "snapshot temperature of the hottest cell at the last time"},
             "scattering_events_per_s": scat / wall, "wall_s": wall, "epochs": epochs,
             "mean_epoch_ms": 1e3 * epoch_s / max(epochs, 1),
-            "mix_vs_alone_max_rel_diff": getattr(serve, "mix_vs_alone", None),
+            "mix_vs_alone_checked": len(kept), "mix_vs_alone_max_rel_diff": worst,
             "mix": {k: kinds.count(k) for k in sorted(set(kinds))}}
+
+
+def main_rel_se(b, res, kind, job):
+    """Relative standard error of a served request's main quantity: the heat flux
+    of a film (the same in every bin), the conductivity of a pore cell, the
+    temperature of the hottest snapshot cell at the last time of a heated spot."""
+    if kind == "film":
+        m, se = res.read(0, b.Q_FLUX)
+        return float(se[0] / max(abs(m[0]), 1e-300))
+    if kind == "pore":
+        m, se = res.read(0, b.Q_KAPPA)
+        return float(se[0] / max(abs(m[0]), 1e-300))
+    m, se = res.read(0, b.Q_SNAPSHOT, len(job.tally.times) - 1)
+    i = int(abs(m).argmax())
+    return float(se[i] / max(abs(m[i]), 1e-300))
 
 
 def copy_probe():
@@ -320,7 +515,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=float, default=1e8, help="particles per film")
-    ap.add_argument("--plain-n", type=float, default=1e6, help="particles per film for the plain-form sample")
+    ap.add_argument("--plain-n", type=float, default=1e7,
+                    help="particles per film of the equal-N comparison with the plain form")
     ap.add_argument("--chunk", type=int, default=0, help="queue chunk (0: autotuned)")
     ap.add_argument("--refill-min", type=int, default=0, help="refill threshold (0: autotuned)")
     ap.add_argument("--block", type=int, default=0, help="workgroup size (0: autotuned)")
@@ -337,6 +533,8 @@ def main():
     ap.add_argument("--serve-class-epochs", action="store_true",
                     help="epochs take one request class at a time, in that class's specialised kernel")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--op-costs", action="store_true",
+                    help="print the instruction-cost probe's VALU slots per operation and exit")
     ap.add_argument("--only", choices=["spot", "nano"], default=None,
                     help="one launch of the heated spot (1e9, 64^3 x 50) or of the 64 nanostructures, "
                          "nothing else (for profiling those kernels)")
@@ -345,6 +543,13 @@ def main():
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.op_costs:
+        from paper_1206_3316_amd import binding as b
+        c = op_costs(b)
+        print(json.dumps({"op_costs_slots": c, "slab_ops_per_flight": sum(v for _, v in slab_items(c)),
+                          "half_ops_per_flight": sum(v for _, v in half_items(c)),
+                          "grad_unit_costs": grad_unit_costs(c)}))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: run with --gpus 1 (sharding particle ranges across GPUs is not implemented)"}))
@@ -404,7 +609,10 @@ def main():
     ms_step = wall * 1e3 / args.steps
     value = scat / wall
     kernel_s = sum(kms) / 1e3
-    achieved = OPS_PER_FLIGHT * flights / kernel_s
+    costs = op_costs(b)
+    items = slab_items(costs)
+    ops_per_flight = sum(v for _, v in items)
+    achieved = ops_per_flight * flights / kernel_s
     out = {
         "metric": "scattering events/s", "value": value, "unit": "scattering events/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
@@ -416,26 +624,23 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "T VALU lane-ops/s", "frac": achieved / PEAK_LANE_OPS,
                      "traffic": TRAFFIC["bytes"] if TRAFFIC["kernel_sha1"] == kernel_sha1() else None,
-                     "kernel": "persistent_kernel<float, GEOM_SLAB>", "ops_per_flight": OPS_PER_FLIGHT,
+                     "kernel": "persistent_kernel<float, GEOM_SLAB>", "ops_per_flight": ops_per_flight,
+                     "ops_items": [[k, round(v, 3)] for k, v in items], "op_costs_slots": costs,
+                     "flights_per_launch": flights / args.steps,
                      "kernel_ms_per_step": kernel_s * 1e3 / args.steps},
     }
     if not args.no_plain:
-        pjobs = di.cross_plane_films(n_per_film=int(args.plain_n), material=mat_in)
-        rp = b.simulate(pjobs, material=mat, precision="fp64", form="plain", stream=stream)
-        sp = rp.stats(-1)
-        rq = b.simulate(pjobs, material=mat, precision="fp32", form="persistent", stream=stream)
-        sq = rq.stats(-1)
-        plain_rate = sp.scatters / (sp.kernel_ms / 1e3)
-        out["plain_form"] = {"scattering_events_per_s": plain_rate, "sample_particles_per_film": int(args.plain_n),
-                             "kernel_ms": sp.kernel_ms,
-                             "persistent_same_sample_events_per_s": sq.scatters / (sq.kernel_ms / 1e3)}
-        out["vs_plain"] = value / plain_rate
+        out["plain_form"] = plain_vs_persistent(b, di, mat, mat_in, stream, int(args.plain_n))
+        out["vs_plain"] = out["plain_form"]["persistent_fp32_over_plain"]
+        out["plain_form"]["headline_over_plain_rate"] = value / out["plain_form"]["plain_fp64_events_per_s"]
     if args.serve_requests > 0:
         out["serving"] = serve(b, di, torch, mat, mat_in, stream, args.serve_requests, args)
         out["p50_latency_s"] = out["serving"]["p50_latency_s"]
         out["p99_latency_s"] = out["serving"]["p99_latency_s"]
+        out["p50_latency_at_1e-3_rel_se_s"] = out["serving"]["p50_latency_at_1e-3_s"]
+        out["p99_latency_at_1e-3_rel_se_s"] = out["serving"]["p99_latency_at_1e-3_s"]
     if not args.no_extra:
-        out["other_workloads"] = other_workloads(b, di, mat, mat_in, stream)
+        out["other_workloads"] = other_workloads(b, di, mat, mat_in, stream, costs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(jobs)
     print(json.dumps(out))

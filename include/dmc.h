@@ -187,9 +187,9 @@ typedef struct {
     int32_t grid_blocks;   /* persistent: workgroups to launch; 0 = fill the device */
     void *workspace;       /* optional caller-owned device memory for tallies and queues */
     size_t workspace_bytes;
-    uint32_t *nscat_out;   /* optional device array (sum of the jobs' n_particles entries): the
-                              scattering events of particle pid of job j are written at
-                              (n_particles of jobs 0..j-1) + pid; not used by the server */
+    uint32_t *nscat_out;   /* optional device array of nscat_out_len entries: the scattering
+                              events of particle pid of job j are written at (n_particles of
+                              jobs 0..j-1) + pid; not used by the server */
     int32_t prio_flights;  /* persistent: a wave holding a particle past this many segments
                               (4x, 16x as many) gets issue priority 1 (2, 3) on its SIMD,
                               so that the few longest trajectories of a heavy-tailed job
@@ -198,6 +198,9 @@ typedef struct {
                               per iteration from 1/16 (1, 16) of this many segments on;
                               0 = 65536, < 0 = off, at most 2^27.  Changes timing only. */
     int32_t pad0;
+    uint64_t nscat_out_len; /* entries of nscat_out; a launch with nscat_out set fails with
+                               DMC_E_INVALID unless this is at least the sum of the jobs'
+                               n_particles (the kernels write one entry per particle) */
 } dmc_run_opts;
 
 /* Fills opts with the defaults (FP32 + FP64 tallies, persistent, auto parameters). */
@@ -348,6 +351,9 @@ typedef struct {
     uint64_t iterations; /* trajectory segments (one per free flight, plus one per periodic face crossed) */
     uint64_t capped;     /* particles stopped by the 2^24-flight safety cap */
     double kernel_ms;    /* device time of the trajectory launch(es), HIP events */
+    uint64_t flights;    /* free flights begun (one random-number block each); iterations - flights
+                            = periodic faces crossed, boundary - (iterations - flights) = wall and
+                            pore-surface interactions */
 } dmc_stats;
 
 /* Waits for the launch; job = -1 gives the launch totals. */
@@ -432,6 +438,20 @@ dmc_status dmc_debug_alias_draw(const dmc_material *m, int32_t which, const uint
 /* FP64 parity-mode logarithm and sin/cos of 2 pi u, evaluated on the device
  * for n host values (out arrays of n, any may be NULL). */
 dmc_status dmc_debug_fp64_math(const double *x, double *log_out, double *sin2pi_out, double *cos2pi_out, size_t n);
+
+/* Instruction-cost probe behind the algorithmic work counts of the roofline:
+ * launches `blocks` workgroups of 256 lanes (0: 32 per compute unit, full
+ * occupancy) in which every lane runs `iters` iterations of four independent
+ * dependency chains of one operation, and times the second of two launches with
+ * HIP events on the null stream.  *ms receives that time and *op_count the number
+ * of operations executed (lanes x iters x 4), so that
+ * slots = ms 1e-3 x (CUs x 64 x clock) / op_count is the VALU issue slots per
+ * lane one operation takes.  op: 0 FP32 FMA (calibration, 1 slot), 1 Philox4x32-10
+ * block with a wave-uniform key (the key schedule on the scalar unit), 2 the
+ * same with a key per lane, 3 v_log_f32, 4 v_sin_f32, 5 v_cos_f32, 6 v_sqrt_f32,
+ * 7 v_rcp_f32, 8 FP64 add.  Allocates and frees a small device buffer.
+ * Errors: DMC_E_INVALID (op out of range, iters = 0), DMC_E_DEVICE. */
+dmc_status dmc_debug_op_cost(int32_t op, uint32_t iters, int32_t blocks, double *ms, uint64_t *op_count);
 
 #ifdef __cplusplus
 }

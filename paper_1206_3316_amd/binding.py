@@ -59,7 +59,8 @@ class dmc_run_opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("form", C.c_int32), ("stream", C.c_void_p), ("block", C.c_int32),
                 ("chunk", C.c_int32), ("refill_min", C.c_int32), ("lds_tally", C.c_int32),
                 ("grid_blocks", C.c_int32), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-                ("nscat_out", C.c_void_p), ("prio_flights", C.c_int32), ("pad0", C.c_int32)]
+                ("nscat_out", C.c_void_p), ("prio_flights", C.c_int32), ("pad0", C.c_int32),
+                ("nscat_out_len", C.c_uint64)]
 
 
 class dmc_job(C.Structure):
@@ -70,7 +71,8 @@ class dmc_job(C.Structure):
 
 class dmc_stats(C.Structure):
     _fields_ = [("particles", C.c_uint64), ("scatters", C.c_uint64), ("boundary", C.c_uint64),
-                ("iterations", C.c_uint64), ("capped", C.c_uint64), ("kernel_ms", C.c_double)]
+                ("iterations", C.c_uint64), ("capped", C.c_uint64), ("kernel_ms", C.c_double),
+                ("flights", C.c_uint64)]
 
 
 class dmc_tune_trial(C.Structure):
@@ -135,6 +137,7 @@ _SIGS = {
     "dmc_debug_alias": ([C.c_void_p, C.c_int32, C.POINTER(C.c_int32), u32p, u32p, C.c_size_t], C.c_int32),
     "dmc_debug_alias_draw": ([C.c_void_p, C.c_int32, u32p, u32p, C.c_size_t], C.c_int32),
     "dmc_debug_fp64_math": ([f64p, f64p, f64p, f64p, C.c_size_t], C.c_int32),
+    "dmc_debug_op_cost": ([C.c_int32, C.c_uint32, C.c_int32, f64p, C.POINTER(C.c_uint64)], C.c_int32),
 }
 
 EXPORTS = tuple(_SIGS)
@@ -391,7 +394,8 @@ def job_struct(job, material: Material, keep: list) -> dmc_job:
 
 
 def run_opts(precision="fp32", form="persistent", stream=None, block=0, chunk=0, refill_min=0, lds_tally=1,
-             grid_blocks=0, workspace=None, workspace_bytes=0, nscat_out=None, prio_flights=0) -> dmc_run_opts:
+             grid_blocks=0, workspace=None, workspace_bytes=0, nscat_out=None, prio_flights=0,
+             nscat_out_len=0) -> dmc_run_opts:
     o = dmc_run_opts()
     dmc_run_opts_default(C.byref(o))
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
@@ -401,6 +405,7 @@ def run_opts(precision="fp32", form="persistent", stream=None, block=0, chunk=0,
     o.workspace = workspace
     o.workspace_bytes = workspace_bytes
     o.nscat_out = nscat_out
+    o.nscat_out_len = int(nscat_out_len)
     o.prio_flights = int(prio_flights)
     return o
 
@@ -462,6 +467,21 @@ class Result:
             pass
 
 
+def _nscat_buffer(nscat_out, n_total: int):
+    """(device pointer, entries) of a per-particle scattering-count tensor: a CUDA
+    tensor of a 4-byte integer dtype with at least one entry per particle of the
+    launch (the kernels write one uint32 per particle)."""
+    if nscat_out is None:
+        return None, 0
+    if not getattr(nscat_out, "is_cuda", False):
+        raise ValueError("nscat_out must be a CUDA tensor")
+    if nscat_out.element_size() != 4 or nscat_out.is_floating_point() or not nscat_out.is_contiguous():
+        raise ValueError("nscat_out must be a contiguous int32 / uint32 tensor")
+    if nscat_out.numel() < n_total:
+        raise ValueError(f"nscat_out has {nscat_out.numel()} entries, the launch has {n_total} particles")
+    return nscat_out.data_ptr(), int(nscat_out.numel())
+
+
 def simulate(jobs, material: Optional[Material] = None, precision="fp32", form="persistent", stream=None,
              workspace=None, nscat_out=None, **params) -> Result:
     """Launch ``dmc_inputs.Job`` objects (one launch; they must share a material).
@@ -483,14 +503,39 @@ def simulate(jobs, material: Optional[Material] = None, precision="fp32", form="
     if workspace is not None:
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
         keep.append(workspace)
-    ns_ptr = None
+    ns_ptr, ns_len = _nscat_buffer(nscat_out, sum(int(j.n_particles) for j in jobs))
     if nscat_out is not None:
-        ns_ptr = nscat_out.data_ptr()
         keep.append(nscat_out)
-    o = run_opts(precision, form, raw_stream, workspace=ws_ptr, workspace_bytes=ws_bytes, nscat_out=ns_ptr, **params)
+    o = run_opts(precision, form, raw_stream, workspace=ws_ptr, workspace_bytes=ws_bytes, nscat_out=ns_ptr,
+                 nscat_out_len=ns_len, **params)
     h = C.c_void_p()
     dmc_simulate_batch(arr, len(jobs), C.byref(o), C.byref(h))
     return Result(h, jobs, keep)
+
+
+def simulate_one(job, material: Optional[Material] = None, precision="fp32", form="persistent", stream=None,
+                 workspace=None, nscat_out=None, **params) -> Result:
+    """One ``dmc_inputs.Job`` through ``dmc_simulate`` (the single-simulation entry
+    point; whole particle range of the job's seed)."""
+    if int(getattr(job, "first_particle", 0)) != 0:
+        raise ValueError("dmc_simulate runs whole particle ranges; use simulate() for slices")
+    material = material or Material(job.material)
+    keep: list = [material]
+    j = job_struct(job, material, keep)
+    raw_stream = getattr(stream, "cuda_stream", stream)
+    ws_ptr, ws_bytes = None, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+        keep.append(workspace)
+    ns_ptr, ns_len = _nscat_buffer(nscat_out, int(job.n_particles))
+    if nscat_out is not None:
+        keep.append(nscat_out)
+    o = run_opts(precision, form, raw_stream, workspace=ws_ptr, workspace_bytes=ws_bytes, nscat_out=ns_ptr,
+                 nscat_out_len=ns_len, **params)
+    h = C.c_void_p()
+    dmc_simulate(j.material, j.geometry, C.byref(j.source), j.n_particles, j.seed, C.byref(j.tally), j.times,
+                 j.n_times, C.byref(o), C.byref(h))
+    return Result(h, [job], keep)
 
 
 TUNED_PARAMS = ("block", "chunk", "refill_min", "lds_tally")
@@ -560,6 +605,22 @@ def debug_fp64_math(x):
     lg, sn, cs = np.zeros(n), np.zeros(n), np.zeros(n)
     dmc_debug_fp64_math(_ptr(x, C.c_double), _ptr(lg, C.c_double), _ptr(sn, C.c_double), _ptr(cs, C.c_double), n)
     return lg, sn, cs
+
+
+OP_COSTS = ("fma", "philox_uniform_key", "philox_lane_key", "log", "sin", "cos", "sqrt", "rcp", "f64_add")
+
+
+def dmc_debug_op_cost(op, iters, blocks, ms, op_count):
+    return _call("dmc_debug_op_cost", op, iters, blocks, ms, op_count)
+
+
+def debug_op_cost(op: str, iters: int, blocks: int = 0):
+    """(kernel ms, operations executed) of the instruction-cost probe for ``op``
+    (one of OP_COSTS)."""
+    ms = C.c_double()
+    n = C.c_uint64()
+    dmc_debug_op_cost(OP_COSTS.index(op), int(iters), int(blocks), C.byref(ms), C.byref(n))
+    return float(ms.value), int(n.value)
 
 
 def debug_philox(seed: int, pid, k, tag) -> np.ndarray:

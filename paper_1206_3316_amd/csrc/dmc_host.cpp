@@ -904,6 +904,13 @@ extern "C" dmc_status dmc_simulate_batch(const dmc_job *jobs, int32_t n_jobs, co
     if (st != DMC_OK) return st;
     std::vector<JobHost> jh;
     if ((st = gather_jobs(jobs, n_jobs, jh)) != DMC_OK) return st;
+    if (o.nscat_out) {
+        uint64_t total = 0;
+        for (const auto &h : jh) total += h.dev.n;
+        if (o.nscat_out_len < total)
+            return fail(DMC_E_INVALID, "nscat_out holds " + std::to_string(o.nscat_out_len) + " entries, the launch has " +
+                                           std::to_string(total) + " particles");
+    }
     return launch(jh, o, out);
 }
 
@@ -1119,6 +1126,7 @@ extern "C" dmc_status dmc_result_stats(const dmc_result *cres, int32_t job, dmc_
         out->boundary += s[2];
         out->iterations += s[3];
         out->capped += s[4];
+        out->flights += s[6];
     }
     out->kernel_ms = R->kernel_ms;
     return DMC_OK;
@@ -1215,6 +1223,37 @@ extern "C" dmc_status dmc_debug_alias_draw(const dmc_material *m, int32_t which,
     (void)hipFree(dw);
     (void)hipFree(ds);
     if (e != hipSuccess) return fail(DMC_E_DEVICE, hipGetErrorString(e));
+    return DMC_OK;
+}
+
+extern "C" dmc_status dmc_debug_op_cost(int32_t op, uint32_t iters, int32_t blocks, double *ms, uint64_t *op_count)
+{
+    if (!ms || !op_count) return fail(DMC_E_INVALID, "NULL argument");
+    if (op < 0 || op >= COST_N) return fail(DMC_E_INVALID, "unknown operation");
+    if (iters == 0 || blocks < 0 || blocks > (1 << 20)) return fail(DMC_E_INVALID, "iters must be > 0, blocks 0..2^20");
+    if (blocks == 0) blocks = device_cus() * 32;
+    uint32_t *d = nullptr;
+    if (hipMalloc(&d, (size_t)blocks * 256 * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DMC_E_NOMEM, "hipMalloc failed");
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    // a first launch loads the code object; the second is timed
+    if (e == hipSuccess) e = launch_op_cost(op, iters, blocks, d, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+    if (e == hipSuccess) e = launch_op_cost(op, iters, blocks, d, nullptr);
+    if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(DMC_E_DEVICE, hipGetErrorString(e));
+    *ms = t;
+    *op_count = (uint64_t)blocks * 256 * (uint64_t)iters * 4;
     return DMC_OK;
 }
 

@@ -14,7 +14,8 @@ constexpr int kMaxBins = 4096;
 constexpr int kMaxTimes = 1024;
 constexpr int kMaxHj = 1024;
 constexpr int kLdsStatJobs = 64;         // per-job counters privatised in LDS up to this many jobs
-constexpr int kStats = 6;                // particles, scatters, boundary, iterations, capped, suspended
+constexpr int kStats = 7;                // particles, scatters, boundary, iterations, capped, suspended,
+                                         // flights (Philox STEP blocks drawn)
 
 enum Geom : int32_t { GEOM_SLAB = 0, GEOM_FILM = 1, GEOM_PORE = 2, GEOM_HALF = 3, GEOM_GRAD = 8, GEOM_ANY = 9 };
 // GEOM_GRAD and GEOM_ANY only select kernel specialisations (see kernel_spec).
@@ -141,6 +142,20 @@ hipError_t launch_debug_philox(uint64_t seed, const uint64_t *pid, const uint32_
 hipError_t launch_debug_alias(const uint32_t *packed, int bits, const uint32_t *words, uint32_t *states, size_t n,
                               hipStream_t stream);
 hipError_t launch_debug_math(const double *x, double *lg, double *sn, double *cs, size_t n, hipStream_t stream);
+// Instruction-cost probes (dmc_debug_op_cost): which operation a probe launch chains.
+enum OpCost : int32_t {
+    COST_FMA = 0,
+    COST_PHILOX_UNIFORM_KEY = 1,
+    COST_PHILOX_LANE_KEY = 2,
+    COST_LOG = 3,
+    COST_SIN = 4,
+    COST_COS = 5,
+    COST_SQRT = 6,
+    COST_RCP = 7,
+    COST_F64_ADD = 8,
+    COST_N = 9
+};
+hipError_t launch_op_cost(int op, uint32_t iters, int blocks, uint32_t *out, hipStream_t stream);
 int max_lds_bytes();
 int occupancy_blocks(int precision, int form, int spec, bool bounded, int block, size_t lds_bytes);
 // The specialised kernel a set of jobs can use.

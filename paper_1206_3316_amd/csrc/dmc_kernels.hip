@@ -1137,7 +1137,8 @@ __device__ void finish(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDe
         tadd(a, sh, p.hl, p.hg, p.n_hj + (int32_t)p.nscat, p.h * p.h);
     }
     if (a.nscat_out) a.nscat_out[J.out_off + (p.pid - J.pid0)] = p.nscat;
-    const unsigned long long vals[kStats] = {1ull, p.nscat, p.nbound, segments<R, G>(p), capped ? 1ull : 0ull};
+    const unsigned long long vals[kStats] = {1ull, p.nscat, p.nbound, segments<R, G>(p), capped ? 1ull : 0ull,
+                                             0ull, p.k};
     if (a.lds_stats) {
 #pragma unroll
         for (int i = 0; i < kStats; ++i)
@@ -1626,7 +1627,92 @@ __global__ void debug_math_kernel(const double *x, double *lg, double *sn, doubl
     cs[i] = c;
 }
 
+// ----------------------------------------------------- instruction costs ----
+
+// Throughput probes behind the algorithmic work counts: every lane runs `iters`
+// iterations of four independent chains of one operation (the operation's
+// result feeds its next input, so nothing can be hoisted or folded).  Launched
+// at full occupancy, the kernel time gives the VALU issue slots per lane one
+// operation takes: slots = time x (CUs x 64 lanes x clock) / (lanes x iters x 4).
+// The Philox chains feed a block's four output words back as the next counter,
+// with the key either wave-uniform (the kernels' usual case: the key schedule
+// runs on the scalar unit) or different in every lane.
+template <int OP>
+__global__ void __launch_bounds__(256) op_cost_kernel(uint32_t iters, uint32_t key0, uint32_t key1, uint32_t *out)
+{
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0;
+    if constexpr (OP == COST_PHILOX_UNIFORM_KEY || OP == COST_PHILOX_LANE_KEY) {
+        const uint32_t k0 = (OP == COST_PHILOX_LANE_KEY) ? key0 ^ gid : key0;
+        const uint32_t k1 = (OP == COST_PHILOX_LANE_KEY) ? key1 + gid : key1;
+        uint4 c[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[j] = make_uint4(gid, (uint32_t)j, 0u, 0u);
+        for (uint32_t i = 0; i < iters; ++i) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c[j] = philox(c[j].x, c[j].y, c[j].z, c[j].w, k0, k1);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc ^= c[j].x ^ c[j].y ^ c[j].z ^ c[j].w;
+    } else if constexpr (OP == COST_F64_ADD) {
+        double d[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) d[j] = (double)(gid + j);
+        const double inc = __uint_as_float(key0 | 0x3f800000u);
+        for (uint32_t i = 0; i < iters; ++i) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) d[j] = d[j] + inc;
+        }
+        acc = (uint32_t)(d[0] + d[1] + d[2] + d[3]);
+    } else {
+        float x[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = 1.0f + (float)(gid & 255u) * 0x1p-9f + (float)j * 0.125f;
+        const float a = __uint_as_float(key0 | 0x3f000000u), b = __uint_as_float(key1 | 0x3c000000u);
+        for (uint32_t i = 0; i < iters; ++i) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if constexpr (OP == COST_FMA) x[j] = fmaf(x[j], a, b);
+                else if constexpr (OP == COST_LOG) x[j] = __builtin_amdgcn_logf(fabsf(x[j]));
+                else if constexpr (OP == COST_SIN) x[j] = __builtin_amdgcn_sinf(x[j]);
+                else if constexpr (OP == COST_COS) x[j] = __builtin_amdgcn_cosf(x[j]);
+                else if constexpr (OP == COST_SQRT) x[j] = __builtin_amdgcn_sqrtf(fabsf(x[j]));
+                else if constexpr (OP == COST_RCP) x[j] = __builtin_amdgcn_rcpf(x[j]);
+            }
+        }
+        acc = __float_as_uint(x[0]) ^ __float_as_uint(x[1]) ^ __float_as_uint(x[2]) ^ __float_as_uint(x[3]);
+    }
+    out[gid] = acc;
+}
+
+template <int OP>
+const void *op_cost_ptr()
+{
+    return (const void *)op_cost_kernel<OP>;
+}
+
 }  // namespace
+
+hipError_t launch_op_cost(int op, uint32_t iters, int blocks, uint32_t *out, hipStream_t stream)
+{
+    const void *f = nullptr;
+    switch (op) {
+    case COST_FMA: f = op_cost_ptr<COST_FMA>(); break;
+    case COST_PHILOX_UNIFORM_KEY: f = op_cost_ptr<COST_PHILOX_UNIFORM_KEY>(); break;
+    case COST_PHILOX_LANE_KEY: f = op_cost_ptr<COST_PHILOX_LANE_KEY>(); break;
+    case COST_LOG: f = op_cost_ptr<COST_LOG>(); break;
+    case COST_SIN: f = op_cost_ptr<COST_SIN>(); break;
+    case COST_COS: f = op_cost_ptr<COST_COS>(); break;
+    case COST_SQRT: f = op_cost_ptr<COST_SQRT>(); break;
+    case COST_RCP: f = op_cost_ptr<COST_RCP>(); break;
+    case COST_F64_ADD: f = op_cost_ptr<COST_F64_ADD>(); break;
+    default: return hipErrorInvalidValue;
+    }
+    uint32_t k0 = 0x12345u, k1 = 0x6789u;
+    uint32_t it = iters;
+    void *params[] = {&it, &k0, &k1, &out};
+    return hipLaunchKernel(f, dim3((unsigned)blocks), dim3(256), params, 0, stream);
+}
 
 hipError_t launch_debug_math(const double *x, double *lg, double *sn, double *cs, size_t n, hipStream_t stream)
 {

@@ -98,7 +98,7 @@ struct Request {
     uint64_t cursor = 0;      // next pid not yet emitted
     uint64_t suspended = 0;   // particles suspended at the end of the last epoch
     double flights_per_particle = 1.0;
-    unsigned long long stats[kStats] = {0, 0, 0, 0, 0, 0};
+    unsigned long long stats[kStats] = {};
     double kernel_ms = 0.0;
     std::vector<double> host_tally;  // filled when complete
 };
@@ -352,7 +352,8 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
     uint64_t n_susp = 0;
     for (size_t i = 0; i < members.size(); ++i) {
         Request *r = members[i];
-        for (int k = 0; k < 5; ++k) r->stats[k] += stats[i * kStats + k];
+        for (int k = 0; k < kStats; ++k)
+            if (k != 5) r->stats[k] += stats[i * kStats + k];  // slot 5 counts this epoch's suspensions
         r->suspended = stats[i * kStats + 5];
         n_susp += r->suspended;
         r->kernel_ms += ms;
@@ -365,6 +366,7 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
         S->totals.boundary += stats[i * kStats + 2];
         S->totals.iterations += stats[i * kStats + 3];
         S->totals.capped += stats[i * kStats + 4];
+        S->totals.flights += stats[i * kStats + 6];
     }
     S->totals.kernel_ms += ms;
     std::swap(S->rest[cls], S->spare);  // the group's particles now wait in what was the spare

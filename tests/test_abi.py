@@ -48,10 +48,10 @@ def layout_probe(tmp_path_factory):
         "dmc_tally_desc": ["n_bins", "n_batches", "kmax", "n_hj", "grid", "grid_lo", "grid_hi", "first_event",
                            "region", "region_c", "region_radius", "region_z"],
         "dmc_run_opts": ["precision", "form", "stream", "block", "chunk", "refill_min", "lds_tally", "grid_blocks",
-                         "workspace", "workspace_bytes", "nscat_out", "prio_flights"],
+                         "workspace", "workspace_bytes", "nscat_out", "prio_flights", "nscat_out_len"],
         "dmc_job": ["material", "geometry", "source", "tally", "n_particles", "seed", "times", "n_times",
                     "first_particle"],
-        "dmc_stats": ["particles", "scatters", "boundary", "iterations", "capped", "kernel_ms"],
+        "dmc_stats": ["particles", "scatters", "boundary", "iterations", "capped", "kernel_ms", "flights"],
         "dmc_server_opts": ["memory_budget", "max_active", "epoch_flights", "drain_flights", "class_epochs", "run"],
         "dmc_trunc_opts": ["n_pilot", "k_pilot", "bias_fraction"],
         "dmc_trunc_plan": ["kmax", "k_uncertain", "fit_ok", "n_fit", "decay", "amplitude", "bias_bound", "kappa_se",

@@ -336,3 +336,91 @@ def test_invalid_jobs_are_rejected():
     job.source.gradient = 0.0
     with pytest.raises(b.DmcError):
         b.simulate([job])
+
+
+# ------------------------------------------- single-simulation entry point ----
+
+def test_dmc_simulate_equals_a_batch_of_one():
+    """dmc_simulate (one simulation, whole particle range) gives a batch of one's
+    tallies, counters and per-particle event counts; in FP64 both equal the oracle."""
+    si = di.silicon_like()
+    mat = b.Material(si)
+    cases = [di.slab_job(si, 200e-9, 20_000, seed=801, n_bins=20),
+             di.pore_cell(80e-9, 0.2, 10_000, seed=802, material=si, kmax=40, n_hj=8),
+             small_spot_job()]
+    for job in cases:
+        for precision in ("fp64", "fp32"):
+            print(f"case {job.name} {precision} dmc_simulate", flush=True)
+            ns1 = torch.zeros(job.n_particles, dtype=torch.int32, device="cuda")
+            ns2 = torch.zeros(job.n_particles, dtype=torch.int32, device="cuda")
+            one = b.simulate_one(job, material=mat, precision=precision, nscat_out=ns1)
+            bat = b.simulate([job], material=mat, precision=precision, nscat_out=ns2)
+            assert rel_diff(one.raw(0), bat.raw(0)) <= 1e-12, job.name
+            s1, s2 = one.stats(0), bat.stats(0)
+            assert (s1.particles, s1.scatters, s1.boundary, s1.iterations) == \
+                (s2.particles, s2.scatters, s2.boundary, s2.iterations)
+            assert torch.equal(ns1, ns2)
+            if precision == "fp64":
+                prep = oracle.prepare(job)
+                oraw, _, ons = oracle.run_raw(job, threads=THREADS, want_nscat=True, prep=prep)
+                worst, ok = compare_sections(lib_sections(job, one.raw(0)), oracle.split_raw(prep, oraw), 1e-9,
+                                             vmax_of(job))
+                assert ok, worst
+                assert np.mean(ns1.cpu().numpy() == ons) >= 0.999
+
+
+def test_per_particle_output_buffer_is_checked_before_launch():
+    """A scattering-count buffer shorter than the launch, on the host, or of a wrong
+    dtype is refused before any kernel runs (the binding and the C entry point)."""
+    si = di.silicon_like()
+    mat = b.Material(si)
+    job = di.slab_job(si, 100e-9, 1000, seed=803, n_bins=20)
+    for bad in (torch.zeros(999, dtype=torch.int32, device="cuda"), torch.zeros(1000, dtype=torch.int32),
+                torch.zeros(1000, dtype=torch.float32, device="cuda"),
+                torch.zeros(1000, dtype=torch.int64, device="cuda")):
+        with pytest.raises(ValueError):
+            b.simulate([job], material=mat, nscat_out=bad)
+    import ctypes as C
+    keep = [mat]
+    arr = (b.dmc_job * 1)()
+    arr[0] = b.job_struct(job, mat, keep)
+    ns = torch.zeros(1000, dtype=torch.int32, device="cuda")
+    o = b.run_opts(nscat_out=ns.data_ptr(), nscat_out_len=999)
+    h = C.c_void_p()
+    rc = b.lib().dmc_simulate_batch(arr, 1, C.byref(o), C.byref(h))
+    assert rc == b.DMC_E_INVALID and h.value is None
+    assert b"nscat_out" in b.lib().dmc_last_error()
+    assert int(ns.abs().sum()) == 0  # nothing was written
+
+
+# ------------------------------------------- planned truncation vs oracle ----
+
+def test_planned_kmax_against_the_oracle():
+    """Truncation planning (the paper's H_j discussion): the planned K_max, run in
+    FP64, reproduces the oracle cut at the same K on the same particle ids; and the
+    oracle's K = 200 conductivity on those particles lies within the planned bias
+    bound plus 3 standard errors of the planned-K value."""
+    si = di.silicon_like()
+    mat = b.Material(si)
+    n = 400_000
+    job = di.pore_cell(100e-9, 0.3, n, seed=611, material=si, kmax=200, n_hj=0)
+    plan = b.plan_truncation(job, material=mat)  # pilot on ids n, n+1, ... of the same seed
+    print("plan", plan, flush=True)
+    K = int(plan["kmax"])
+    assert plan["fit_ok"] == 1 and plan["n_fit"] < K < 200
+    assert plan["bias_bound"] <= 0.2 * plan["kappa_se"] * 1.0001
+    cut = di.pore_cell(100e-9, 0.3, n, seed=611, material=si, kmax=K, n_hj=0)
+    prep = oracle.prepare(cut)
+    oraw, ocnt, ons = oracle.run_raw(cut, threads=THREADS, want_nscat=True, prep=prep)
+    ores = oracle.finalize(prep, oraw)
+    res, raw, st, nscat = run_lib(cut, "fp64", "persistent")
+    assert np.mean(nscat == ons) >= 0.999
+    assert int(nscat.max()) <= K
+    worst, ok = compare_sections(lib_sections(cut, raw), oracle.split_raw(prep, oraw), 1e-9, vmax_of(cut))
+    assert ok, worst
+    full, *_ = oracle.simulate(job, threads=THREADS)
+    kK = float(ores["kappa"])
+    k200, se200 = float(full["kappa"]), float(full["kappa_se"])
+    print(f"kappa at K={K}: {kK:.5f}; at K=200: {k200:.5f} +- {se200:.5f}; bound {plan['bias_bound']:.5f}",
+          flush=True)
+    assert abs(kK - k200) <= plan["bias_bound"] + 3.0 * se200
