@@ -127,9 +127,12 @@ def nongray_slab(C, v, tau, L: float, dT1: float = 0.5, dT2: float = -0.5, n_bin
     and energy conservation in scattering fixes psi as the (C_m / tau_m)-weighted
     mean of <e_m> / C_m over states.  psi is taken piecewise constant on a mesh
     that is refined toward the walls, and the equation is imposed on cell averages
-    (every kernel and source term integrated exactly with E2 / E3).  Returns bin
-    averages of the energy temperature T = sum_m <e_m> / C_tot, of the
-    pseudo-temperature psi, and the heat flux
+    (every kernel and source term integrated exactly with E2 / E3).  The cells
+    must not be much wider than the free paths that carry the gain weight: for
+    cells wider than a free path, cell averages exchange energy at a rate set by
+    the cell width instead of the free path.  Returns bin averages of the energy
+    temperature T = sum_m <e_m> / C_tot, of the pseudo-temperature psi, and the
+    heat flux
 
         q = sum_m v_m C_m / 2 [dT1 E3(x / lam) - dT2 E3((L - x) / lam)
                                + (1/lam) (int_0^x psi E2((x - x') / lam) dx'
@@ -145,23 +148,28 @@ def nongray_slab(C, v, tau, L: float, dT1: float = 0.5, dT2: float = -0.5, n_bin
     a, b = e[:-1], e[1:]
     dx = b - a
     n = a.shape[0]
-    A = np.zeros((n, n))
+    A = np.zeros((n, n))  # sum_m w_m / 2 <pair integral> / dx_i   (psi -> psi)
+    B = np.zeros((n, n))  # sum_m C_m / 2 <pair integral> / dx_i   (psi -> sum_m <e_m>)
     rhs = np.zeros(n)
-    src_cell = np.zeros((lam.shape[0], n))  # cell averages of the wall terms of <e_m> / C_m
+    src_T = np.zeros(n)
+    iu = np.triu_indices(n + 1)
     for m in range(lam.shape[0]):
         lm = lam[m]
-        s = 0.5 * dT1 * lm * (_E(3, a / lm) - _E(3, b / lm)) + 0.5 * dT2 * lm * (_E(3, (L - b) / lm) - _E(3, (L - a) / lm))
-        src_cell[m] = s / dx
-        rhs += w[m] * src_cell[m]
-        A += (0.5 * w[m]) * _pair_integral(a[:, None], b[:, None], a[None, :], b[None, :], lm) / dx[:, None]
+        # H(e_p - e_q) for every pair of edges (symmetric); the pair integral of cells i, j
+        # is H(b_i - a_j) - H(a_i - a_j) - H(b_i - b_j) + H(a_i - b_j)
+        Hm = np.zeros((n + 1, n + 1))
+        Hm[iu] = _H(e[iu[0]] - e[iu[1]], lm)
+        Hm = Hm + np.triu(Hm, 1).T
+        P = Hm[1:, :-1] - Hm[:-1, :-1] - Hm[1:, 1:] + Hm[:-1, 1:]
+        P /= dx[:, None]
+        src = (0.5 * dT1 * lm * (_E(3, a / lm) - _E(3, b / lm))
+               + 0.5 * dT2 * lm * (_E(3, (L - b) / lm) - _E(3, (L - a) / lm))) / dx
+        rhs += w[m] * src
+        src_T += C[m] * src
+        A += (0.5 * w[m]) * P
+        B += (0.5 * C[m]) * P
     psi = np.linalg.solve(np.eye(n) - A, rhs)
-    # energy temperature: sum_m C_m <e_m> / C_m over cells, then bins
-    T_cell = np.zeros(n)
-    for m in range(lam.shape[0]):
-        lm = lam[m]
-        K = 0.5 * _pair_integral(a[:, None], b[:, None], a[None, :], b[None, :], lm) / dx[:, None]
-        T_cell += C[m] * (src_cell[m] + K @ psi)
-    T_cell /= np.sum(C)
+    T_cell = (src_T + B @ psi) / np.sum(C)
     edges = np.linspace(0.0, L, n_bins + 1)
     k = np.clip(np.searchsorted(edges, 0.5 * (a + b)) - 1, 0, n_bins - 1)
     T_bin = np.bincount(k, weights=T_cell * dx, minlength=n_bins) / np.diff(edges)
@@ -169,10 +177,10 @@ def nongray_slab(C, v, tau, L: float, dT1: float = 0.5, dT2: float = -0.5, n_bin
 
     def flux_at(x):
         q = 0.0
+        left = a < x
         for m in range(lam.shape[0]):
             lm = lam[m]
-            left = (a < x)
-            # int_a^b psi E2(|x - x'| / lam) dx' / lam = E3 differences, per side
+            # int over a cell of psi E2(|x - x'| / lam) dx' / lam = E3 differences, per side
             il = np.sum(psi[left] * (_E(3, np.maximum(x - b[left], 0.0) / lm) - _E(3, (x - a[left]) / lm)))
             ir = np.sum(psi[~left] * (_E(3, (a[~left] - x) / lm) - _E(3, (b[~left] - x) / lm)))
             q += 0.5 * v[m] * C[m] * (dT1 * _E(3, x / lm) - dT2 * _E(3, (L - x) / lm) + il - ir)

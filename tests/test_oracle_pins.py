@@ -654,3 +654,39 @@ def test_pore_mean_chord_is_cauchys(porosity):
     ref2 = math.pi * solid / (2.0 * math.pi * r)
     assert abs(mean3 / ref3 - 1.0) < 0.03, (mean3, ref3)
     assert abs(mean2 / ref2 - 1.0) < 0.03, (mean2, ref2)
+
+
+# ------------------------- frequency-dependent slab, heated spot, specular pore ----
+# The checks live in tests/pinlib.py so that tests/test_oracle_mutants.py can run
+# them against oracles with planted mistakes.
+
+import pinlib  # noqa: E402
+
+
+@pytest.mark.parametrize("L,n,seed", [(100e-9, 200_000, 91), (300e-9, 100_000, 92)])
+def test_nongray_slab_matches_integral_equation(L, n, seed):
+    """Frequency-dependent slab (80 silicon-like states): T, T_loc and q agree with
+    the pseudo-temperature integral equation solved deterministically."""
+    pinlib.check_nongray_slab(oracle, L=L, n=n, seed=seed)
+
+
+def test_nongray_reference_reduces_to_the_gray_solution():
+    """The frequency-dependent solver with a single state is the gray slab of the
+    Nystrom solver (two independent discretisations of one equation)."""
+    lam = 100e-9 / 0.998
+    T, P, q0, qL = refsol.nongray_slab([1.0], [1.0], [lam], 100e-9, per_bin=20, h_min=lam * 1e-3)
+    gb, gpsi = refsol.gray_slab_richardson(0.998, n_bins=20, M=600)
+    assert np.allclose(T, gb, atol=2e-5) and np.allclose(P, gb, atol=2e-5)
+    assert q0 == pytest.approx(gpsi / 4.0, rel=1e-4) and qL == pytest.approx(q0, rel=1e-9)
+
+
+def test_snapshot_estimator_ballistic_limit():
+    pinlib.check_snapshot_ballistic(oracle)
+
+
+def test_snapshot_estimator_diffusive_limit():
+    pinlib.check_snapshot_diffusive(oracle)
+
+
+def test_specular_pore_projected_chord_is_santalos():
+    pinlib.check_specular_pore_chords(oracle)
