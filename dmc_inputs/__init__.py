@@ -49,6 +49,9 @@ class Material:
     branches: List[Branch]
     T_eq: float = 300.0
     name: str = ""
+    # mean cosine of the angle between the directions before and after a
+    # scattering event (Henyey-Greenstein phase function); 0: isotropic
+    scatter_g: float = 0.0
 
     @property
     def n_states(self) -> int:
@@ -62,7 +65,7 @@ class Material:
 
 
 def gray_material(vg: float = 6000.0, tau: float = 16.7e-12, omega: float = 1.0e13,
-                  T_eq: float = 300.0, dos_domega: float = 7.25e28) -> Material:
+                  T_eq: float = 300.0, dos_domega: float = 7.25e28, scatter_g: float = 0.0) -> Material:
     """A single-mode (gray) material: one state with the given speed and relaxation time.
 
     D*domega defaults to about 1e6 / k_B so the mode's heat capacity is of
@@ -70,7 +73,7 @@ def gray_material(vg: float = 6000.0, tau: float = 16.7e-12, omega: float = 1.0e
     exact value does not matter.
     """
     b = Branch(omega=[omega], domega=[1.0], dos=[dos_domega], vg=[vg], tau=[tau], degeneracy=1.0)
-    return Material([b], T_eq=T_eq, name="gray")
+    return Material([b], T_eq=T_eq, name="gray", scatter_g=scatter_g)
 
 
 SILICON_LATTICE = 5.431e-10  # m
@@ -80,7 +83,7 @@ def silicon_like(n_bins: int = 1000, T_eq: float = 300.0,
                  omega_max=(7.7e13, 3.0e13), degeneracy=(1.0, 2.0),
                  A: float = 1.3e-45, B: float = 9e-19, C: float = 190.0,
                  L_b: float = math.inf, lattice: float = SILICON_LATTICE,
-                 tau_scale: float = 1.0) -> Material:
+                 tau_scale: float = 1.0, scatter_g: float = 0.0) -> Material:
     """Silicon-like material: isotropic sine dispersion, LA + doubly-degenerate TA.
 
     omega(k) = omega_max sin(pi k / (2 k_max)), k_max = 2 pi / a.
@@ -104,7 +107,7 @@ def silicon_like(n_bins: int = 1000, T_eq: float = 300.0,
             inv_tau = inv_tau + vg / L_b
         tau = tau_scale / inv_tau
         branches.append(Branch(w, dw, dos, vg, tau, g))
-    return Material(branches, T_eq=T_eq, name="silicon_like")
+    return Material(branches, T_eq=T_eq, name="silicon_like", scatter_g=scatter_g)
 
 
 # --------------------------------------------------------------------------

@@ -74,8 +74,14 @@ typedef struct {
  * FP64, builds the exact-integer alias tables of the initial (~C), wall-flux
  * (~C v) and post-scattering gain (~C / tau, Eq. (2)) distributions, and
  * uploads device copies.  Total states must be 1..65536.
- * Errors: DMC_E_INVALID (non-finite or non-positive inputs), DMC_E_DEVICE. */
-dmc_status dmc_material_create(const dmc_branch *branches, int32_t n_branches, double T_eq, dmc_material **out);
+ * scatter_g: the direction after a scattering event (step IVb).  0 draws it
+ * isotropically, as the paper's step states; g in (-1, 1) draws it from the
+ * Henyey-Greenstein phase function of mean cosine g about the incoming
+ * direction, the generalisation the paper allows there (the state is still
+ * redrawn from Eq. (2)).  First-event termination needs g = 0.
+ * Errors: DMC_E_INVALID (non-finite or non-positive inputs, |g| >= 1), DMC_E_DEVICE. */
+dmc_status dmc_material_create(const dmc_branch *branches, int32_t n_branches, double T_eq, double scatter_g,
+                               dmc_material **out);
 dmc_status dmc_material_destroy(dmc_material *m);
 
 /* sums[0] = C_tot = sum C_m [J/m^3/K], sums[1] = G_tau = sum C_m / tau_m,

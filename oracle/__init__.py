@@ -73,6 +73,7 @@ class Problem(C.Structure):
         ("region_kind", C.c_int32), ("region_c", C.c_double * 2), ("region_r", C.c_double),
         ("region_z", C.c_double * 2),
         ("field_n", C.c_int32 * 2), ("field_lo", C.c_double * 2), ("field_hi", C.c_double * 2),
+        ("scatter_g", C.c_double),
     ]
 
 
@@ -115,6 +116,7 @@ def lib():
             L.oracle_emit.argtypes = [C.POINTER(Problem), C.c_uint64, f64p, f64p, u32p, f64p]
             L.oracle_pore_chords.argtypes = [C.POINTER(Problem), C.c_uint64, C.c_uint64, C.c_uint32, f64p, f64p]
             L.oracle_pore_chords.restype = C.c_uint64
+            L.oracle_scatter_direction.argtypes = [C.c_double, C.c_uint32, C.c_uint32, f64p, f64p]
             _lib = L
     return _lib
 
@@ -287,6 +289,12 @@ def prepare(job: di.Job) -> Prepared:
     P.first_event = int(bool(getattr(tl, "first_event", False)))
     if P.first_event and (job.geometry.kind != "film_x" or job.source.kind != "gradient"):
         raise ValueError("first-event termination applies to in-plane films under the gradient source")
+    P.scatter_g = float(getattr(mat, "scatter_g", 0.0))
+    if not -1.0 < P.scatter_g < 1.0:
+        raise ValueError("the mean scattering cosine g must lie in (-1, 1)")
+    if P.first_event and P.scatter_g != 0.0:
+        raise ValueError("first-event termination needs isotropic scattering (the flux after a scattering "
+                         "event averages to zero only then)")
     if tl.kmax >= 0 and tl.n_hj > tl.kmax:
         raise ValueError("n_hj must not exceed kmax")
     times = np.ascontiguousarray(tl.times, dtype=np.float64)
@@ -337,6 +345,14 @@ def emit_state(prep: "Prepared", pid: int):
     s = C.c_double(0.0)
     lib().oracle_emit(C.byref(prep.struct), int(pid), _p(x, C.c_double), _p(o, C.c_double), C.byref(m), C.byref(s))
     return x, o, int(m.value), float(s.value)
+
+
+def scatter_direction(g: float, w2: int, w3: int, o_in) -> np.ndarray:
+    """Step IVb's new direction for incoming direction o_in and words w2, w3."""
+    oi = np.ascontiguousarray(o_in, dtype=np.float64)
+    out = np.zeros(3)
+    lib().oracle_scatter_direction(float(g), int(w2), int(w3), _p(oi, C.c_double), _p(out, C.c_double))
+    return out
 
 
 def pore_chords(prep: "Prepared", pid_begin: int, pid_end: int, n_chords: int):

@@ -318,6 +318,9 @@ typedef struct {
      * [field_lo, field_hi) in (x, z) (0 cells: none); Eq. (4) in every cell */
     int32_t field_n[2];
     double field_lo[2], field_hi[2];
+    /* mean cosine g of the angle between the directions before and after a
+     * scattering event (Henyey-Greenstein phase function); 0: isotropic */
+    double scatter_g;
 } oracle_problem;
 
 typedef struct {
@@ -378,6 +381,37 @@ static void isotropic(uint32_t w2, uint32_t w3, double o[3])
 {
     double mu = 2.0 * unif(w2) - 1.0;
     dir_about(mu, unif(w3), EZ, EX, EY, o);
+}
+
+/* Direction after a scattering event (step IVb).  g = 0: isotropic, the step as
+ * the paper states it.  g != 0: the generalisation the paper allows there; the
+ * cosine mu of the angle to the incoming direction n follows the Henyey-Greenstein
+ * phase function p(mu) = (1 - g^2) / (2 (1 + g^2 - 2 g mu)^(3/2)) of mean g,
+ * drawn by inverting its cumulative distribution,
+ *   mu = (1 + g^2 - f^2) / (2 g),  f = (1 - g^2) / (1 - g + 2 g u),
+ * and the azimuth is uniform in the frame t1 = (n_x n_z, n_y n_z, -s) / s,
+ * t2 = (-n_y, n_x, 0) / s, s = sqrt(n_x^2 + n_y^2) (x, y for n along z). */
+static void scatter_direction(double g, uint32_t w2, uint32_t w3, double o[3])
+{
+    if (g == 0.0) {
+        isotropic(w2, w3, o);
+        return;
+    }
+    double u = unif(w2);
+    double f = (1.0 - g * g) / (1.0 - g + 2.0 * g * u);
+    double mu = (1.0 + g * g - f * f) / (2.0 * g);
+    if (mu > 1.0) mu = 1.0;
+    if (mu < -1.0) mu = -1.0;
+    double n[3] = {o[0], o[1], o[2]};
+    double s2 = n[0] * n[0] + n[1] * n[1];
+    if (s2 > 1e-12) {
+        double s = sqrt(s2);
+        double t1[3] = {n[0] * n[2] / s, n[1] * n[2] / s, -s};
+        double t2[3] = {-n[1] / s, n[0] / s, 0.0};
+        dir_about(mu, unif(w3), n, t1, t2, o);
+    } else {
+        dir_about(mu, unif(w3), n, EX, EY, o);
+    }
 }
 
 /* Lambertian (cosine-weighted) direction about an inward normal: mu = sqrt(u).
@@ -783,7 +817,7 @@ int oracle_run(const oracle_problem *P, uint64_t pid0, uint64_t pid1, double *ta
             } else {                                                  /* step IVb */
                 p.m = alias_draw(w[1], P->gain_bits, P->gain_thresh, P->gain_alias);
                 if (scatter_hist) scatter_hist[p.m] += 1;
-                isotropic(w[2], w[3], p.o);
+                scatter_direction(P->scatter_g, w[2], w[3], p.o);
                 p.last = OR_NO_SURFACE;
                 ++nscat;
                 cnt->scatters++;
@@ -890,6 +924,13 @@ uint64_t oracle_pore_chords(const oracle_problem *P, uint64_t pid0, uint64_t pid
     *sum_len = s3;
     *sum_len_xz = s2;
     return done;
+}
+
+/* Step IVb's direction for one incoming direction and two words, exported for the tests. */
+void oracle_scatter_direction(double g, uint32_t w2, uint32_t w3, const double o_in[3], double o_out[3])
+{
+    for (int i = 0; i < 3; ++i) o_out[i] = o_in[i];
+    scatter_direction(g, w2, w3, o_out);
 }
 
 /* Raw Philox words for one (seed, pid, k, tag), exported for the tests. */

@@ -104,7 +104,8 @@ class dmc_server_opts(C.Structure):
 _SIGS = {
     "dmc_last_error": ([], C.c_char_p),
     "dmc_version": ([], C.c_char_p),
-    "dmc_material_create": ([C.POINTER(dmc_branch), C.c_int32, C.c_double, C.POINTER(C.c_void_p)], C.c_int32),
+    "dmc_material_create": ([C.POINTER(dmc_branch), C.c_int32, C.c_double, C.c_double, C.POINTER(C.c_void_p)],
+                            C.c_int32),
     "dmc_material_destroy": ([C.c_void_p], C.c_int32),
     "dmc_material_info": ([C.c_void_p, C.POINTER(C.c_int32), f64p], C.c_int32),
     "dmc_geometry_create": ([C.POINTER(dmc_geometry_desc), C.POINTER(C.c_void_p)], C.c_int32),
@@ -179,8 +180,8 @@ def _call(name, *args):
 
 # thin wrappers with the C names -------------------------------------------
 
-def dmc_material_create(branches, n_branches, T_eq, out):
-    return _call("dmc_material_create", branches, n_branches, T_eq, out)
+def dmc_material_create(branches, n_branches, T_eq, scatter_g, out):
+    return _call("dmc_material_create", branches, n_branches, T_eq, scatter_g, out)
 
 
 def dmc_material_destroy(m):
@@ -301,7 +302,8 @@ class Material:
             self._keep += arrs
             brs[i] = dmc_branch(arrs[0].shape[0], *[_ptr(a, C.c_double) for a in arrs], float(b.degeneracy))
         h = C.c_void_p()
-        dmc_material_create(brs, len(material.branches), float(material.T_eq), C.byref(h))
+        dmc_material_create(brs, len(material.branches), float(material.T_eq),
+                            float(getattr(material, "scatter_g", 0.0)), C.byref(h))
         self.handle = h
 
     def info(self):

@@ -152,7 +152,48 @@ namespace dmc {
 
 // --------------------------------------------------------- job validation ----
 
+// Two-entry alias table of the wall-source powers, packed for the device, with
+// the rule of build_alias (largest-remainder integer masses summing to 2^32, then
+// Vose's pairing): the under-full column keeps its mass and aliases the other,
+// which is left full.  Written without containers so that every launch path can
+// use it.
+static void alias_two(double w0, double w1, uint32_t packed[2])
+{
+    const double W = w0 + w1;
+    const double s0 = (w0 / W) * 4294967296.0, s1 = (w1 / W) * 4294967296.0;
+    uint64_t q[2] = {(uint64_t)std::floor(s0), (uint64_t)std::floor(s1)};
+    const double f[2] = {s0 - std::floor(s0), s1 - std::floor(s1)};
+    uint64_t rem = (uint64_t(1) << 32) - q[0] - q[1];
+    const int first = (f[1] > f[0]) ? 1 : 0;  // ties: the lower index first
+    for (int r = 0; rem > 0; ++r, --rem) q[r == 0 ? first : 1 - first] += 1;
+    const uint64_t U = uint64_t(1) << 31;
+    uint32_t thresh[2] = {(uint32_t)U, (uint32_t)U}, alias[2] = {0u, 1u};
+    if (q[0] < U) {
+        thresh[0] = (uint32_t)q[0];
+        alias[0] = 1;
+    } else if (q[1] < U) {
+        thresh[1] = (uint32_t)q[1];
+        alias[1] = 0;
+    }
+    for (uint32_t j = 0; j < 2; ++j) packed[j] = pack_alias(thresh[j], alias[j], j, 1);
+}
+
 dmc_status prepare_job(const dmc_job &jb, JobHost &h)
+{
+    JobMeta meta;
+    dmc_status st = prepare_job_core(jb, h.dev, meta);
+    if (st != DMC_OK) return st;
+    h.job = jb;
+    h.geom = jb.geometry->d;
+    h.times.assign(jb.times, jb.times + jb.n_times);
+    h.power = meta.power;
+    h.avg_volume = meta.avg_volume;
+    h.size = meta.size;
+    h.hidden = meta.hidden;
+    return DMC_OK;
+}
+
+dmc_status prepare_job_core(const dmc_job &jb, JobDev &d, JobMeta &h)
 {
     if (!jb.material || !jb.geometry) return fail(DMC_E_INVALID, "job without material or geometry");
     const dmc_material &M = *jb.material;
@@ -169,17 +210,16 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
         return fail(DMC_E_INVALID, "n_hj must be in 0..kmax");
     if (t.first_event != 0 && (t.first_event != 1 || g.kind != DMC_GEOM_FILM_X || s.kind != DMC_SRC_GRADIENT))
         return fail(DMC_E_INVALID, "first_event applies to in-plane films under the gradient source");
+    if (t.first_event && M.scatter_g != 0.0)
+        return fail(DMC_E_INVALID, "first_event needs isotropic scattering (scatter_g = 0)");
     if (jb.n_times < 0 || jb.n_times > kMaxTimes || (jb.n_times > 0 && !jb.times))
         return fail(DMC_E_INVALID, "bad snapshot times");
-    h.job = jb;
-    h.geom = g;
-    h.times.assign(jb.times, jb.times + jb.n_times);
     for (int i = 0; i < jb.n_times; ++i)
-        if (!finite_pos(h.times[i]) || (i > 0 && !(h.times[i] > h.times[i - 1])))
+        if (!finite_pos(jb.times[i]) || (i > 0 && !(jb.times[i] > jb.times[i - 1])))
             return fail(DMC_E_INVALID, "snapshot times must be positive and increasing");
     const bool transient = jb.n_times > 0;
-    JobDev &d = h.dev;
     std::memset(&d, 0, sizeof(d));
+    h = JobMeta{};
     d.n = jb.n_particles;
     d.pid0 = jb.first_particle;
     d.key0 = (uint32_t)jb.seed;
@@ -229,13 +269,7 @@ dmc_status prepare_job(const dmc_job &jb, JobHost &h)
         if (nsrc == 0) return fail(DMC_E_INVALID, "no isothermal wall differs from T_eq");
         d.n_src = nsrc;
         h.power = (nsrc == 2) ? pw[0] + pw[1] : pw[0];
-        if (nsrc == 2) {
-            AliasTable st;
-            std::string why;
-            if (!build_alias({pw[0], pw[1]}, st, why)) return fail(DMC_E_INVALID, why);
-            d.src_packed[0] = st.packed[0];
-            d.src_packed[1] = st.packed[1];
-        }
+        if (nsrc == 2) alias_two(pw[0], pw[1], d.src_packed);
         h.avg_volume = g.length;
     } else if (s.kind == DMC_SRC_GRADIENT) {
         if (!(std::isfinite(s.gradient) && s.gradient != 0.0)) return fail(DMC_E_INVALID, "zero gradient");
@@ -404,19 +438,35 @@ int kernel_spec(const JobDev *jobs, int n_jobs)
     return slab ? (int)GEOM_SLAB : half ? (int)GEOM_HALF : grad ? (int)GEOM_GRAD : (int)GEOM_ANY;
 }
 
-dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, const std::vector<double> &times,
-                          std::vector<JobDev> &table, const LaunchBuffers &b, size_t tally_doubles, bool zero_tally,
-                          const dmc_run_opts &o, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+int launch_spec(const dmc_material *M, const JobDev *devs, int n_jobs)
 {
-    const int n_jobs = (int)devs.size();
-    const int spec = kernel_spec(devs.data(), n_jobs);
+    const int spec = kernel_spec(devs, n_jobs);
+    // the slab kernel follows the z direction cosine alone, which suffices for
+    // isotropic scattering only
+    return (spec == GEOM_SLAB && M->scatter_g != 0.0) ? (int)GEOM_ANY : spec;
+}
+
+dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const LaunchBuffers &b, const dmc_run_opts &o,
+                       LaunchPlan &plan)
+{
+    const int spec = launch_spec(M, devs, n_jobs);
     KArgs a{};
+    {
+        const double g = M->scatter_g;
+        a.scatter_g = g;
+        a.hg[0] = 1.0 - g * g;
+        a.hg[1] = 1.0 - g;
+        a.hg[2] = 2.0 * g;
+        a.hg[3] = 1.0 + g * g;
+        for (int i = 0; i < 4; ++i) a.hgf[i] = (float)a.hg[i];
+        a.hgf_inv2g = g != 0.0 ? (float)(1.0 / (2.0 * g)) : 0.0f;
+    }
     a.jobs = b.jobs;
     a.n_jobs = n_jobs;
     a.K = M->K;
     a.qbegin = 0;
     a.total = 0;
-    for (auto &d : devs) a.total += d.n;
+    for (int i = 0; i < n_jobs; ++i) a.total += devs[i].n;
     a.queue = b.queue;
     a.gain_bits = M->gain.bits;
     a.flux_bits = M->flux.bits;
@@ -447,7 +497,8 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
         return fail(DMC_E_INVALID, "time-bounded launches need the persistent form");
     if (b.n_resume && !b.drain_iters) return fail(DMC_E_INVALID, "resuming needs a time-bounded launch");
     const size_t stats_lds = a.lds_stats ? (size_t)n_jobs * kStats * 8 : 0;
-    for (auto &d : devs) {
+    for (int i = 0; i < n_jobs; ++i) {
+        JobDev &d = devs[i];
         d.lds_bins = d.lds_kappa = d.lds_hj = d.lds_dispx = d.lds_region = d.lds_field = -1;
         d.disp_tel = (o.form == DMC_FORM_PERSISTENT && spec == GEOM_SLAB && !(b.drain_iters || b.n_resume)) ? 1 : 0;
     }
@@ -462,7 +513,8 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
         const size_t budget = (cap - tab - stats_lds - 16) / 8;  // doubles
         int32_t lo = 0;
         if (o.lds_tally) {
-            for (auto &d : devs) {
+            for (int i = 0; i < n_jobs; ++i) {
+                JobDev &d = devs[i];
                 if (d.off_bins >= 0) {
                     const int32_t n = d.n_batches * 3 * d.n_bins;
                     if ((size_t)(lo + n) <= budget) {
@@ -488,7 +540,8 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
                 }
             }
             // fields last: they are large, and the small sections of every job come first
-            for (auto &d : devs) {
+            for (int i = 0; i < n_jobs; ++i) {
+                JobDev &d = devs[i];
                 if (d.off_field < 0) continue;
                 const int64_t n = (int64_t)d.n_batches * 2 * d.grid[0] * d.grid[2];
                 if ((size_t)(lo + n) <= budget) {
@@ -499,8 +552,8 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
         }
         a.lds_tally_doubles = lo;
         a.bins_lds_all = 1;
-        for (auto &d : devs)
-            if (d.off_bins >= 0 && d.lds_bins < 0) a.bins_lds_all = 0;
+        for (int i = 0; i < n_jobs; ++i)
+            if (devs[i].off_bins >= 0 && devs[i].lds_bins < 0) a.bins_lds_all = 0;
         lds_bytes = ((tab + 15) & ~size_t(15)) + (size_t)lo * 8 + stats_lds;
         a.chunk = o.chunk > 0 ? o.chunk : 1024;
         a.refill_min = o.refill_min > 0 ? o.refill_min : 16;
@@ -523,6 +576,43 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
         a.refill_min = 64;
         lds_bytes = stats_lds;
     }
+    plan.a = a;
+    plan.material = M;
+    plan.spec = spec;
+    plan.block = block;
+    plan.grid = grid;
+    plan.lds_bytes = lds_bytes;
+    return DMC_OK;
+}
+
+dmc_status submit_launch(const LaunchPlan &plan, const JobDev *devs, int n_jobs, const dmc_run_opts &o, hipStream_t s)
+{
+    if (o.form == DMC_FORM_PERSISTENT) {
+        DMC_HIP_OR_FAIL(launch_trajectories(plan.a, o.precision, o.form, plan.spec, plan.block, plan.grid,
+                                            plan.lds_bytes, s));
+    } else {
+        // one launch per simulation, in order, on the same stream
+        for (int i = 0; i < n_jobs; ++i) {
+            KArgs aj = plan.a;
+            aj.qbegin = devs[i].base;
+            aj.total = devs[i].base + devs[i].n;
+            const uint64_t blocks = (devs[i].n + 255) / 256;
+            if (blocks > 0x7fffffffull) return fail(DMC_E_INVALID, "too many particles for one plain launch");
+            DMC_HIP_OR_FAIL(launch_trajectories(aj, o.precision, o.form, launch_spec(plan.material, &devs[i], 1), 256,
+                                                (int)blocks, plan.lds_bytes, s));
+        }
+    }
+    return DMC_OK;
+}
+
+dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, const std::vector<double> &times,
+                          std::vector<JobDev> &table, const LaunchBuffers &b, size_t tally_doubles, bool zero_tally,
+                          const dmc_run_opts &o, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    const int n_jobs = (int)devs.size();
+    LaunchPlan plan;
+    dmc_status st = plan_launch(M, devs.data(), n_jobs, b, o, plan);
+    if (st != DMC_OK) return st;
     // the device table is ordered by queue position (the kernels search it by base)
     table = devs;
     std::stable_sort(table.begin(), table.end(), [](const JobDev &x, const JobDev &y) { return x.base < y.base; });
@@ -533,20 +623,8 @@ dmc_status enqueue_launch(const dmc_material *M, std::vector<JobDev> &devs, cons
                                 (size_t)n_jobs * kStats, s));
     DMC_HIP_OR_FAIL(launch_fill(nullptr, 0, b.queue, 2, s));
     DMC_HIP_OR_FAIL(hipEventRecord(ev0, s));
-    if (o.form == DMC_FORM_PERSISTENT) {
-        DMC_HIP_OR_FAIL(launch_trajectories(a, o.precision, o.form, spec, block, grid, lds_bytes, s));
-    } else {
-        // one launch per simulation, in order, on the same stream
-        for (int i = 0; i < n_jobs; ++i) {
-            KArgs aj = a;
-            aj.qbegin = devs[i].base;
-            aj.total = devs[i].base + devs[i].n;
-            const uint64_t blocks = (devs[i].n + 255) / 256;
-            if (blocks > 0x7fffffffull) return fail(DMC_E_INVALID, "too many particles for one plain launch");
-            DMC_HIP_OR_FAIL(launch_trajectories(aj, o.precision, o.form, kernel_spec(&devs[i], 1), 256, (int)blocks,
-                                                lds_bytes, s));
-        }
-    }
+    st = submit_launch(plan, devs.data(), n_jobs, o, s);
+    if (st != DMC_OK) return st;
     DMC_HIP_OR_FAIL(hipEventRecord(ev1, s));
     return DMC_OK;
 }
@@ -594,12 +672,16 @@ Layout layout_of(const std::vector<JobHost> &jh)
 // Expected flights per particle, used to queue the longest trajectories first:
 // trajectory lengths are heavy-tailed, and the longest single particle bounds
 // a launch's duration unless it starts early.
+static double expected_flights(const dmc_material &M, const JobDev &d, double length, double t_final)
+{
+    if (d.src == SRC_WALLS) return 2.0 * length * M.G_tau / M.G_v + 1.0;
+    if (d.src == SRC_GAUSSIAN) return t_final * M.G_tau / M.C_tot + 1.0;
+    return d.kmax >= 0 ? 1.5 * d.kmax + 1.0 : 1000.0;
+}
+
 double flights_per_particle(const dmc_material &M, const JobHost &h)
 {
-    const JobDev &d = h.dev;
-    if (d.src == SRC_WALLS) return 2.0 * h.geom.length * M.G_tau / M.G_v + 1.0;
-    if (d.src == SRC_GAUSSIAN) return h.times.back() * M.G_tau / M.C_tot + 1.0;
-    return d.kmax >= 0 ? 1.5 * d.kmax + 1.0 : 1000.0;
+    return expected_flights(M, h.dev, h.geom.length, h.times.empty() ? 0.0 : h.times.back());
 }
 
 // Flights of the longest trajectory a gradient job is likely to hold, when one
@@ -607,54 +689,49 @@ double flights_per_particle(const dmc_material &M, const JobHost &h)
 // of mean length Lambda crosses a film or pore cell of size l about Lambda / l
 // times, each crossing or wall hit being one flight.  Among N particles the
 // longest free path is drawn from about the states whose emission weight above
-// it is 1/N.  Jobs with such a tail go first, so that it runs beside the bulk
-// of the launch rather than after it.
-double longest_flights(const dmc_material &M, const JobHost &h)
+// it is 1/N (the material keeps its free paths sorted with the running sum of
+// C v).  Jobs with such a tail go first, so that it runs beside the bulk of the
+// launch rather than after it.
+static double longest_flights(const dmc_material &M, const JobDev &d, double cell)
 {
-    const JobDev &d = h.dev;
-    const double cell = h.geom.length;
     if (d.src != SRC_GRADIENT || !(cell > 0.0) || d.n == 0) return 0.0;
-    std::vector<std::pair<double, double>> lw(M.K);
-    for (int m = 0; m < M.K; ++m) lw[m] = {M.v[m] * M.tau[m], M.C[m] * M.v[m]};
-    std::sort(lw.begin(), lw.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
     const double target = M.G_v / (double)d.n;
-    double cum = 0.0;
-    for (const auto &e : lw) {
-        cum += e.second;
-        if (cum >= target) return e.first / cell;
-    }
-    return 0.0;
+    const auto it = std::lower_bound(M.cv_cum.begin(), M.cv_cum.end(), target);
+    if (it == M.cv_cum.end()) return 0.0;
+    return M.lam_desc[(size_t)(it - M.cv_cum.begin())] / cell;
 }
 
-dmc_status gather_jobs(const dmc_job *jobs, int32_t n_jobs, std::vector<JobHost> &jh)
+void queue_order(const dmc_material &M, const JobDev *devs, const double *length, const double *t_final, int n_jobs,
+                 int *rank, double *key)
 {
-    if (!jobs || n_jobs < 1 || n_jobs > kMaxJobs) return fail(DMC_E_INVALID, "n_jobs must be 1..4096");
-    jh.resize(n_jobs);
-    const dmc_material *M = jobs[0].material;
     for (int i = 0; i < n_jobs; ++i) {
-        if (jobs[i].material != M) return fail(DMC_E_INVALID, "all jobs of a launch must share one material");
-        dmc_status st = prepare_job(jobs[i], jh[i]);
-        if (st != DMC_OK) return st;
+        key[i] = std::max(expected_flights(M, devs[i], length[i], t_final[i]), longest_flights(M, devs[i], length[i]));
+        rank[i] = i;
     }
-    // queue order: descending expected flights per particle, or the flights of a
-    // gradient job's longest likely trajectory where that is larger (ties:
-    // caller's order)
-    std::vector<int> order(n_jobs);
-    for (int i = 0; i < n_jobs; ++i) order[i] = i;
-    std::vector<double> f(n_jobs);
-    for (int i = 0; i < n_jobs; ++i) f[i] = std::max(flights_per_particle(*M, jh[i]), longest_flights(*M, jh[i]));
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return f[x] > f[y]; });
+    // stable insertion sort, descending key (a batch holds at most a few thousand jobs)
+    for (int i = 1; i < n_jobs; ++i) {
+        const int v = rank[i];
+        int p = i - 1;
+        while (p >= 0 && key[rank[p]] < key[v]) {
+            rank[p + 1] = rank[p];
+            --p;
+        }
+        rank[p + 1] = v;
+    }
+}
+
+void assign_offsets(JobDev *devs, const int64_t *size, const int32_t *n_times, const int *rank, int n_jobs)
+{
     uint64_t base = 0;
     for (int r = 0; r < n_jobs; ++r) {
-        JobDev &d = jh[order[r]].dev;
-        if (base + d.n < base) return fail(DMC_E_INVALID, "particle count overflow");
+        JobDev &d = devs[rank[r]];
         d.base = base;
         base += d.n;
     }
     int64_t toff = 0, tim = 0;
     uint64_t out = 0;
     for (int i = 0; i < n_jobs; ++i) {
-        JobDev &d = jh[i].dev;
+        JobDev &d = devs[i];
         d.stat_slot = i;
         d.out_off = out;
         out += d.n;
@@ -666,10 +743,40 @@ dmc_status gather_jobs(const dmc_job *jobs, int32_t n_jobs, std::vector<JobHost>
         if (d.off_dispx >= 0) d.off_dispx += toff;
         if (d.off_region >= 0) d.off_region += toff;
         if (d.off_field >= 0) d.off_field += toff;
-        toff += jh[i].size;
+        toff += size[i];
         d.times_off = (int32_t)tim;
-        tim += (int64_t)jh[i].times.size();
+        tim += n_times[i];
     }
+}
+
+dmc_status gather_jobs(const dmc_job *jobs, int32_t n_jobs, std::vector<JobHost> &jh)
+{
+    if (!jobs || n_jobs < 1 || n_jobs > kMaxJobs) return fail(DMC_E_INVALID, "n_jobs must be 1..4096");
+    jh.resize(n_jobs);
+    const dmc_material *M = jobs[0].material;
+    uint64_t total = 0;
+    for (int i = 0; i < n_jobs; ++i) {
+        if (jobs[i].material != M) return fail(DMC_E_INVALID, "all jobs of a launch must share one material");
+        dmc_status st = prepare_job(jobs[i], jh[i]);
+        if (st != DMC_OK) return st;
+        if (total + jh[i].dev.n < total) return fail(DMC_E_INVALID, "particle count overflow");
+        total += jh[i].dev.n;
+    }
+    std::vector<JobDev> devs(n_jobs);
+    std::vector<double> len(n_jobs), tf(n_jobs), key(n_jobs);
+    std::vector<int64_t> size(n_jobs);
+    std::vector<int32_t> nt(n_jobs);
+    std::vector<int> rank(n_jobs);
+    for (int i = 0; i < n_jobs; ++i) {
+        devs[i] = jh[i].dev;
+        len[i] = jh[i].geom.length;
+        tf[i] = jh[i].times.empty() ? 0.0 : jh[i].times.back();
+        size[i] = jh[i].size;
+        nt[i] = (int32_t)jh[i].times.size();
+    }
+    queue_order(*M, devs.data(), len.data(), tf.data(), n_jobs, rank.data(), key.data());
+    assign_offsets(devs.data(), size.data(), nt.data(), rank.data(), n_jobs);
+    for (int i = 0; i < n_jobs; ++i) jh[i].dev = devs[i];
     return DMC_OK;
 }
 
@@ -767,15 +874,18 @@ extern "C" dmc_status dmc_workspace_size(const dmc_job *jobs, int32_t n_jobs, co
 extern "C" const char *dmc_last_error(void) { return dmc::g_err.c_str(); }
 extern "C" const char *dmc_version(void) { return "dmc 0.1 gfx950"; }
 
-extern "C" dmc_status dmc_material_create(const dmc_branch *br, int32_t nbr, double T_eq, dmc_material **out)
+extern "C" dmc_status dmc_material_create(const dmc_branch *br, int32_t nbr, double T_eq, double scatter_g,
+                                         dmc_material **out)
 {
     if (!out) return fail(DMC_E_INVALID, "out is NULL");
     *out = nullptr;
     if (!br || nbr < 1) return fail(DMC_E_INVALID, "need at least one branch");
     if (!finite_pos(T_eq)) return fail(DMC_E_INVALID, "T_eq must be positive");
+    if (!(scatter_g > -1.0 && scatter_g < 1.0)) return fail(DMC_E_INVALID, "scatter_g must lie in (-1, 1)");
     std::unique_ptr<dmc_material> M(new (std::nothrow) dmc_material());
     if (!M) return fail(DMC_E_NOMEM, "host allocation failed");
     M->T_eq = T_eq;
+    M->scatter_g = scatter_g;
     std::vector<double> wg, wi, wf;
     for (int b = 0; b < nbr; ++b) {
         const dmc_branch &B = br[b];
@@ -806,6 +916,19 @@ extern "C" dmc_status dmc_material_create(const dmc_branch *br, int32_t nbr, dou
     }
     M->K = (int32_t)M->v.size();
     if (M->K > 65536) return fail(DMC_E_INVALID, "more than 65536 states");
+    {
+        // free paths in descending order with the running sum of the wall-flux weight C v
+        // (the longest trajectory a batch job is likely to hold, see longest_flights)
+        std::vector<std::pair<double, double>> lw(M->K);
+        for (int m = 0; m < M->K; ++m) lw[m] = {M->v[m] * M->tau[m], M->C[m] * M->v[m]};
+        std::sort(lw.begin(), lw.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+        double cum = 0.0;
+        for (const auto &e : lw) {
+            cum += e.second;
+            M->lam_desc.push_back(e.first);
+            M->cv_cum.push_back(cum);
+        }
+    }
     std::string why;
     if (!build_alias(wg, M->gain, why) || !build_alias(wi, M->init, why) || !build_alias(wf, M->flux, why))
         return fail(DMC_E_INVALID, "material: " + why);

@@ -43,7 +43,18 @@ struct JobHost {
     JobDev dev{};
 };
 
+// Normalisation and tally size of a job, as prepare_job_core computes them.
+struct JobMeta {
+    double power = 0.0;
+    double avg_volume = 1.0;
+    int64_t size = 0;
+    int64_t hidden = 0;
+};
+
 dmc_status prepare_job(const dmc_job &jb, JobHost &h);
+// Validates a job and fills its device descriptor (offsets relative to the job's
+// block) and normalisation, without allocating.
+dmc_status prepare_job_core(const dmc_job &jb, JobDev &d, JobMeta &meta);
 // Host-side completion of a job's tally block after the copy from the device
 // (offsets of d relative to block): fills the sections the device skips.
 void complete_tally(const JobDev &d, double *block);
@@ -67,6 +78,35 @@ struct LaunchBuffers {
     // bulk rate rather than its longest particle; 0 = the safety cap
     uint32_t iter_cap = 0;
 };
+
+// Launch geometry of a batch: kernel specialisation, arguments (LDS plan,
+// chunk, refill threshold), workgroup size and count.
+struct LaunchPlan {
+    KArgs a{};
+    const struct ::dmc_material *material = nullptr;
+    int spec = 0, block = 0, grid = 0;
+    size_t lds_bytes = 0;
+};
+
+// The kernel specialisation for a launch of these jobs of material M.
+int launch_spec(const struct ::dmc_material *M, const JobDev *devs, int n_jobs);
+// Chooses the kernel and plans LDS privatisation and occupancy for devs (whose
+// LDS offsets it sets); host work only, no allocation.
+dmc_status plan_launch(const struct ::dmc_material *M, JobDev *devs, int n_jobs, const LaunchBuffers &b,
+                       const dmc_run_opts &o, LaunchPlan &plan);
+// Enqueues the trajectory launch(es) of a plan on stream s.
+dmc_status submit_launch(const LaunchPlan &plan, const JobDev *devs, int n_jobs, const dmc_run_opts &o, hipStream_t s);
+// Launch order of jobs: descending expected flights per particle, or the flights
+// of a gradient job's longest likely trajectory where that is larger (ties:
+// caller's order).  length: slab / film / cell size per job; t_final: last
+// snapshot time (transient jobs).  rank[r] = job index; key: scratch of n_jobs.
+// No allocation.
+void queue_order(const struct ::dmc_material &M, const JobDev *devs, const double *length, const double *t_final,
+                 int n_jobs, int *rank, double *key);
+// Queue bases in rank order, and tally / time / per-particle-output offsets in
+// job order (size: doubles of each job's tally block, n_times: its snapshot
+// times).  No allocation.
+void assign_offsets(JobDev *devs, const int64_t *size, const int32_t *n_times, const int *rank, int n_jobs);
 
 // Plans LDS privatisation and occupancy, uploads the descriptors, clears the
 // counters (and the tallies if zero_tally), records ev0, enqueues the
@@ -95,7 +135,9 @@ struct dmc_material {
     int32_t K = 0;
     double T_eq = 0.0;
     std::vector<double> v, tau, C;
+    std::vector<double> lam_desc, cv_cum;  // free paths, descending, and the running sum of C v
     double C_tot = 0.0, G_tau = 0.0, G_v = 0.0;
+    double scatter_g = 0.0;  // mean cosine of the scattering angle (Henyey-Greenstein); 0: isotropic
     dmc::AliasTable gain, init, flux;
     uint32_t *d_gain = nullptr, *d_init = nullptr, *d_flux = nullptr;
     float4 *d_st32 = nullptr;

@@ -113,6 +113,12 @@ struct KArgs {
     Suspended *suspend_out;
     uint32_t suspend_cap;
     uint32_t iter_cap;              // segments after which a particle is stopped and counted as capped
+    // scattering direction (step IVb): g = 0 isotropic; else Henyey-Greenstein of mean
+    // cosine g, mu = (hg[3] - f^2) / hg[2] with f = hg[0] / (hg[1] + hg[2] u):
+    // hg = {1 - g^2, 1 - g, 2 g, 1 + g^2} (FP64 and FP32 copies, and 1 / (2 g))
+    double scatter_g;
+    double hg[4];
+    float hgf[4], hgf_inv2g;
     uint32_t prio_flights;          // persistent: waves holding a particle past this many flights (4x,
                                     // 16x) get SIMD issue priority 1 (2, 3); 0: off; at most 2^27
 };

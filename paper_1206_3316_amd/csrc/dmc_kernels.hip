@@ -158,6 +158,13 @@ struct Pr<double> {
     __device__ static double mu(uint32_t w) { return 2.0 * u(w) - 1.0; }
     // FP64 keeps the reference's arithmetic unchanged
     __device__ static double nonneg(double t) { return t; }
+    // Henyey-Greenstein polar cosine, the reference's operations in its order
+    __device__ static double hg_mu(const KArgs &a, uint32_t w)
+    {
+        const double f = a.hg[0] / (a.hg[1] + a.hg[2] * u(w));
+        const double m = (a.hg[3] - f * f) / a.hg[2];
+        return m > 1.0 ? 1.0 : (m < -1.0 ? -1.0 : m);
+    }
 };
 
 template <>
@@ -186,6 +193,12 @@ struct Pr<float> {
     __device__ static float mu(uint32_t w) { return fmaf(one_plus(w), 2.0f, -3.0f) + 0x1p-23f; }
     // a position rounded just past a wall must not yield a negative flight time
     __device__ static float nonneg(float t) { return fmaxf(t, 0.0f); }
+    // Henyey-Greenstein polar cosine through reciprocals
+    __device__ static float hg_mu(const KArgs &a, uint32_t w)
+    {
+        const float f = a.hgf[0] * __builtin_amdgcn_rcpf(fmaf(a.hgf[2], u(w), a.hgf[1]));
+        return fminf(fmaxf((a.hgf[3] - f * f) * a.hgf_inv2g, -1.0f), 1.0f);
+    }
 };
 
 // ------------------------------------------------------------ lane state ----
@@ -330,6 +343,34 @@ __device__ __forceinline__ void isotropic(Lane<R> &p, uint32_t w2, uint32_t w3)
     p.ox = st * c;
     p.oy = st * s;
     p.oz = mu;
+}
+
+// Direction after a scattering event with a Henyey-Greenstein phase function
+// (the generalisation of step IVb): polar cosine mu about the incoming direction
+// n, uniform azimuth in the frame t1 = (n_x n_z, n_y n_z, -s) / s,
+// t2 = (-n_y, n_x, 0) / s, s = sqrt(n_x^2 + n_y^2) (x, y when n is along z);
+// the FP64 form follows the reference's operations.
+template <typename R>
+__device__ __forceinline__ void scatter_hg(Lane<R> &p, const KArgs &a, uint32_t w2, uint32_t w3)
+{
+    const R mu = Pr<R>::hg_mu(a, w2);
+    R c, s;
+    Pr<R>::cs(w3, c, s);
+    const R st = Pr<R>::sq((R)1 - mu * mu);
+    const R nx = p.ox, ny = p.oy, nz = p.oz;
+    const R s2 = nx * nx + ny * ny;
+    R t1x = (R)1, t1y = (R)0, t1z = (R)0, t2x = (R)0, t2y = (R)1, t2z = (R)0;
+    if (s2 > (R)1e-12) {
+        const R sn = Pr<R>::sq(s2);
+        t1x = Pr<R>::div(nx * nz, sn);
+        t1y = Pr<R>::div(ny * nz, sn);
+        t1z = -sn;
+        t2x = Pr<R>::div(-ny, sn);
+        t2y = Pr<R>::div(nx, sn);
+    }
+    p.ox = mu * nx + st * (c * t1x + s * t2x);
+    p.oy = mu * ny + st * (c * t1y + s * t2y);
+    p.oz = mu * nz + st * (c * t1z + s * t2z);
 }
 
 // Per-particle copies of its job's parameters.
@@ -1273,7 +1314,12 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
         } else {                                                          // step IVb
             const uint32_t m = alias_draw(sh.gain, a.gain_bits, w.y);
             load_state(p, a, sh, m);
-            isotropic(p, w.z, w.w);
+            // the slab kernel runs isotropic scattering only (it tracks the z direction
+            // cosine alone); launches with another phase function take the generic kernel
+            if (G == GEOM_SLAB || a.scatter_g == 0.0)
+                isotropic(p, w.z, w.w);
+            else
+                scatter_hg(p, a, w.z, w.w);
             p.last = kNoSurface;
             if (gradient && p.nscat < (uint32_t)p.n_hj) {
                 tadd(a, sh, p.hl, p.hg, (int32_t)p.nscat, p.h);

@@ -24,55 +24,11 @@
 #include <vector>
 
 #include "dmc_host_internal.h"
+#include "dmc_sched.h"
 
 using namespace dmc;
 
 namespace {
-
-// First-fit allocator over [0, size) with coalescing; 256-byte granules.
-class Arena {
-public:
-    explicit Arena(size_t size) { free_[0] = size; }
-    bool alloc(size_t bytes, size_t &off)
-    {
-        bytes = (bytes + 255) & ~size_t(255);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                off = it->first;
-                const size_t rest = it->second - bytes;
-                free_.erase(it);
-                if (rest) free_[off + bytes] = rest;
-                used_[off] = bytes;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off)
-    {
-        auto u = used_.find(off);
-        if (u == used_.end()) return;
-        size_t start = off, len = u->second;
-        used_.erase(u);
-        auto next = free_.lower_bound(start);
-        if (next != free_.end() && start + len == next->first) {
-            len += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == start) {
-                start = prev->first;
-                len += prev->second;
-                free_.erase(prev);
-            }
-        }
-        free_[start] = len;
-    }
-
-private:
-    std::map<size_t, size_t> free_, used_;
-};
 
 // Epoch classes: the kernel specialisation a request runs in when an epoch
 // holds only its class (wall-driven slabs, transient half spaces, gradient
@@ -110,7 +66,7 @@ struct dmc_server {
     dmc_server_opts opts{};
     std::mutex mu;
     void *arena_mem = nullptr;
-    std::unique_ptr<Arena> arena;
+    std::unique_ptr<sched::Arena> arena;
     void *scratch = nullptr;
     LaunchBuffers sb;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -183,7 +139,8 @@ extern "C" dmc_status dmc_server_create(const dmc_material *material, const dmc_
         S->arena_mem = nullptr;
         return fail(DMC_E_NOMEM, "cannot allocate the server's memory budget");
     }
-    S->arena.reset(new Arena(opts->memory_budget));
+    S->arena.reset(new (std::nothrow) sched::Arena(opts->memory_budget));
+    if (!S->arena) return fail(DMC_E_NOMEM, "host allocation failed");
     const size_t nj = (size_t)opts->max_active;
     const size_t jb = a256(nj * sizeof(JobDev)), tb = a256(nj * kMaxTimes * sizeof(double)),
                  stb = a256(nj * kStats * 8), qb = a256(16);
@@ -261,39 +218,40 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
     {
         std::lock_guard<std::mutex> g(S->mu);
         // admit in arrival order while a slot and memory are free
-        while (!S->pending.empty() && (int)S->active.size() < S->opts.max_active) {
-            Request *r = S->pending.front().get();
-            size_t off;
-            if (!S->arena->alloc(r->bytes, off)) break;
-            r->arena_off = off;
-            DMC_HIP_OR_FAIL(launch_fill((double *)((char *)S->arena_mem + off), r->bytes / 8, nullptr, 0, s));
-            S->active.push_back(std::move(S->pending.front()));
-            S->pending.pop_front();
+        {
+            const int room = std::max(0, S->opts.max_active - (int)S->active.size());
+            const int look = std::min<int>(room, (int)S->pending.size());
+            std::vector<size_t> want(look), off(look);
+            for (int i = 0; i < look; ++i) want[i] = S->pending[i]->bytes;
+            const int n_in = sched::admit(*S->arena, want.data(), look, (int)S->active.size(), S->opts.max_active,
+                                          off.data());
+            for (int i = 0; i < n_in; ++i) {
+                S->pending.front()->arena_off = off[i];
+                S->active.push_back(std::move(S->pending.front()));
+                S->pending.pop_front();
+            }
+            for (int i = 0; i < n_in; ++i) {
+                const Request *r = S->active[S->active.size() - (size_t)n_in + (size_t)i].get();
+                DMC_HIP_OR_FAIL(launch_fill((double *)((char *)S->arena_mem + r->arena_off), r->bytes / 8, nullptr, 0, s));
+            }
         }
         if (S->active.empty()) return DMC_OK;
         // the epoch's group: the next class, in turn, with admitted requests
         // (always group 0 without class epochs)
         bool has[kClasses] = {false, false, false, false};
         for (auto &rp : S->active) has[rp->cls] = true;
-        for (int k = 0; k < kClasses; ++k) {
-            const int c = (S->next_class + k) % kClasses;
-            if (has[c]) {
-                cls = c;
-                break;
-            }
-        }
+        cls = sched::next_group(has, kClasses, S->next_class);
+        if (cls < 0) return fail(DMC_E_DEVICE, "internal: no epoch group");
         S->next_class = (cls + 1) % kClasses;
         size_t n_members = 0;
         for (auto &rp : S->active) n_members += (rp->cls == cls) ? 1 : 0;
         const double epoch_flights = S->opts.epoch_flights ? (double)S->opts.epoch_flights : 2.0e10;
-        const double share = epoch_flights / (double)n_members;
         uint64_t base = 0;
         for (auto &rp : S->active) {
             Request *r = rp.get();
             if (r->cls != cls) continue;
             const uint64_t left = r->jh.dev.n - r->cursor;
-            uint64_t n = (uint64_t)std::max(256.0, share / r->flights_per_particle);
-            n = std::min(n, left);
+            const uint64_t n = sched::slice(epoch_flights, n_members, r->flights_per_particle, left);
             JobDev d = r->jh.dev;
             const int64_t shift = (int64_t)(r->arena_off / sizeof(double));
             if (d.off_bins >= 0) d.off_bins += shift;
@@ -318,14 +276,10 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
         // epoch's job table (jobs are queued in member order, so index = member)
         S->h_resume_job.assign((size_t)S->opts.max_active, 0);
         const std::vector<Request *> &pm = S->prev_members[cls];
-        for (size_t i = 0; i < pm.size(); ++i) {
-            if (S->prev_suspended[cls][i] == 0) continue;  // no particle of this slot resumes
-            int32_t idx = -1;
-            for (size_t j = 0; j < members.size(); ++j)
-                if (members[j] == pm[i]) idx = (int32_t)j;
-            if (idx < 0) return fail(DMC_E_DEVICE, "internal: a request with suspended particles left the epoch");
-            S->h_resume_job[i] = idx;
-        }
+        std::vector<const void *> prev_keys(pm.begin(), pm.end()), keys(members.begin(), members.end());
+        if (!sched::resume_map(prev_keys.data(), S->prev_suspended[cls].data(), pm.size(), keys.data(), keys.size(),
+                               S->h_resume_job.data(), S->h_resume_job.size()))
+            return fail(DMC_E_DEVICE, "internal: a request with suspended particles left the epoch");
     }
     DMC_HIP_OR_FAIL(hipMemcpyAsync(S->d_resume_job, S->h_resume_job.data(), S->h_resume_job.size() * sizeof(int32_t),
                                    hipMemcpyHostToDevice, s));

@@ -147,3 +147,48 @@ def check_specular_pore_chords(orc, porosity=0.3, n=20_000, seed=95):
     assert m > 0.95 * 40 * job.n_particles
     ref2 = math.pi * (P * P - math.pi * r * r) / (2.0 * math.pi * r)
     assert abs((s2 / m) / ref2 - 1.0) < 0.03, (s2 / m, ref2)
+
+
+# ------------------------------------------------ anisotropic scattering ----
+
+def check_hg_bulk(orc, g=0.6, n=300_000, seed=96):
+    """Gray bulk with Henyey-Greenstein scattering: kappa = C v^2 tau / (3 (1 - g))
+    within 4 standard errors (a free path keeps g^j of the initial direction after
+    j events on average)."""
+    mat = di.gray_material(scatter_g=g)
+    _, Cm, _ = orc.tabulate(mat)
+    om, dom, dos, vg, tau, deg = mat.flat()
+    ref = float(np.sum(Cm * vg * vg * tau) / 3.0) / (1.0 - g)
+    job = di.pore_cell(200e-9, 0.0, n, seed, material=mat, kmax=60, n_hj=0)
+    res, *_ = orc.simulate(job, threads=THREADS)
+    assert res["kappa_se"] < 0.02 * ref
+    assert abs(res["kappa"] - ref) <= 4 * res["kappa_se"], (res["kappa"], ref, res["kappa_se"])
+
+
+def _hg_cdf(mu, g):
+    return (1.0 - g * g) / (2.0 * g) * ((1.0 + g * g - 2.0 * g * mu) ** -0.5 - 1.0 / (1.0 + g))
+
+
+def check_hg_sampler(orc, g=0.6, n=40_000, seed=61):
+    """Scattering directions for g != 0: unit vectors whose cosine to the incoming
+    direction follows the Henyey-Greenstein law (KS against its cumulative
+    distribution, mean g, second moment (1 + 2 g^2) / 3), with a uniform azimuth
+    (no mean sideways component)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = rng.integers(0, 2 ** 32, size=(n, 2), dtype=np.uint64)
+    v = rng.normal(size=(n, 3))
+    v[:50] = [0.0, 0.0, 1.0]  # along the frame's axis
+    v[50:100] = [0.0, 0.0, -1.0]
+    o_in = v / np.linalg.norm(v, axis=1)[:, None]
+    o_out = np.array([orc.scatter_direction(g, int(a), int(b), o) for (a, b), o in zip(w, o_in)])
+    assert np.allclose(np.linalg.norm(o_out, axis=1), 1.0, atol=1e-12)
+    mu = np.sum(o_in * o_out, axis=1)
+    assert stats.kstest(mu, lambda m: _hg_cdf(np.asarray(m), g)).pvalue > 1e-3
+    assert abs(mu.mean() - g) < 4.0 * mu.std() / math.sqrt(n)
+    m2 = np.mean(mu ** 2)
+    assert abs(m2 - (1.0 + 2.0 * g * g) / 3.0) < 4.0 * np.std(mu ** 2) / math.sqrt(n)
+    side = o_out - mu[:, None] * o_in  # component normal to the incoming direction
+    ref = np.cross(o_in, np.array([0.3, -0.5, 0.8]))
+    ref /= np.linalg.norm(ref, axis=1)[:, None]
+    proj = np.sum(side * ref, axis=1)
+    assert abs(proj.mean()) < 4.0 * proj.std() / math.sqrt(n)

@@ -88,7 +88,7 @@ def test_ctypes_structures_match_c_layout(layout_probe):
 def test_invalid_arguments_fail_cleanly_without_a_device():
     """Validation happens before any HIP call and reports a message."""
     out = C.c_void_p(123)
-    rc = b.lib().dmc_material_create(None, 0, 300.0, C.byref(out))
+    rc = b.lib().dmc_material_create(None, 0, 300.0, 0.0, C.byref(out))
     assert rc == b.DMC_E_INVALID and out.value is None
     assert b"branch" in b.lib().dmc_last_error()
     br = (b.dmc_branch * 1)()
@@ -96,8 +96,12 @@ def test_invalid_arguments_fail_cleanly_without_a_device():
     ones = np.ones(2)
     p = lambda a: a.ctypes.data_as(b.f64p)
     br[0] = b.dmc_branch(2, p(om), p(ones), p(ones), p(ones), p(ones), 1.0)
-    rc = b.lib().dmc_material_create(br, 1, 300.0, C.byref(out))
+    rc = b.lib().dmc_material_create(br, 1, 300.0, 0.0, C.byref(out))
     assert rc == b.DMC_E_INVALID and b"non-physical" in b.lib().dmc_last_error()
+    om[1] = 2e13
+    for g in (1.0, -1.0, float("nan")):
+        rc = b.lib().dmc_material_create(br, 1, 300.0, g, C.byref(out))
+        assert rc == b.DMC_E_INVALID and b"scatter_g" in b.lib().dmc_last_error()
     d = b.dmc_geometry_desc()
     d.kind = 7
     rc = b.lib().dmc_geometry_create(C.byref(d), C.byref(out))

@@ -46,6 +46,12 @@ MUTANTS = [
     ("pore normal taken from the cell corner instead of the pore axis", "dmc_oracle.c",
      "double nx = p->x[0] - c, nz = p->x[2] - c;", "double nx = p->x[0], nz = p->x[2];",
      ["check_specular_pore_chords"]),
+    ("Henyey-Greenstein cosine with the sign of g reversed", "dmc_oracle.c",
+     "double mu = (1.0 + g * g - f * f) / (2.0 * g);", "double mu = (1.0 + g * g - f * f) / (-2.0 * g);",
+     ["check_hg_bulk"]),
+    ("scattering frame vector t1 left unnormalised", "dmc_oracle.c",
+     "double t1[3] = {n[0] * n[2] / s, n[1] * n[2] / s, -s};", "double t1[3] = {n[0] * n[2], n[1] * n[2], -s};",
+     ["check_hg_sampler"]),
 ]
 
 SCRIPT = """

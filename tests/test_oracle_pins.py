@@ -690,3 +690,44 @@ def test_snapshot_estimator_diffusive_limit():
 
 def test_specular_pore_projected_chord_is_santalos():
     pinlib.check_specular_pore_chords(oracle)
+
+
+# ---------------------------------------- anisotropic scattering (step IVb) ----
+
+@pytest.mark.parametrize("g", [0.6, -0.4, 0.95])
+def test_henyey_greenstein_directions(g):
+    """Scattering directions for g != 0 (pinlib.check_hg_sampler)."""
+    pinlib.check_hg_sampler(oracle, g=g)
+
+
+def test_isotropic_case_is_unchanged():
+    """g = 0 is the paper's isotropic step: the same directions as before."""
+    o = np.array([0.6, 0.0, 0.8])
+    for a, b in ((1, 2), (2 ** 31, 77), (2 ** 32 - 1, 5)):
+        d = oracle.scatter_direction(0.0, a, b, o)
+        mu = 2.0 * ((a + 0.5) / 2.0 ** 32) - 1.0
+        assert d[2] == mu
+
+
+@pytest.mark.parametrize("g", [0.6, -0.4])
+def test_bulk_conductivity_with_anisotropic_scattering(g):
+    """Gray bulk (periodic cell without a pore) under the gradient source: a free
+    path keeps on average g^j of the initial z direction after j scattering events,
+    so kappa = C v^2 tau / (3 (1 - g)) (the transport relaxation time tau / (1 - g)),
+    and the flux carried between events j and j+1 is H_j = H_0 g^j."""
+    mat = di.gray_material(scatter_g=g)
+    _, _, _, kb = _kappa_bulk(mat)
+    job = di.pore_cell(200e-9, 0.0, 400_000, seed=62, material=mat, kmax=60, n_hj=4)
+    res, *_ = oracle.simulate(job, threads=THREADS)
+    ref = kb / (1.0 - g)
+    assert abs(res["kappa"] - ref) <= 4 * res["kappa_se"], (res["kappa"], ref, res["kappa_se"])
+    assert res["kappa_se"] < 0.02 * ref
+    hj, se = res["hj"], res["hj_se"]
+    for j in (1, 2, 3):
+        assert abs(hj[j] - hj[0] * g ** j) <= 4 * np.hypot(se[j], se[0] * abs(g) ** j), (j, hj, se)
+
+
+def test_first_event_rejected_with_anisotropic_scattering():
+    job = di.in_plane_film(50e-9, 0.0, 10, seed=1, material=di.gray_material(scatter_g=0.3), first_event=True)
+    with pytest.raises(ValueError):
+        oracle.prepare(job)
