@@ -244,6 +244,35 @@ dmc_status dmc_simulate(const dmc_material *material, const dmc_geometry *geomet
  * Asynchronous on opts->stream. */
 dmc_status dmc_simulate_batch(const dmc_job *jobs, int32_t n_jobs, const dmc_run_opts *opts, dmc_result **out);
 
+/* ---- The batched launch for callers that cannot allocate ----
+ * For code that must not allocate device memory: HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  Runs the jobs like
+ * dmc_simulate_batch (same kernels, same realisation) but allocates nothing:
+ * job descriptors, snapshot times, counters, the particle queue and the device
+ * tally blocks live in one fixed 32 MiB device array per GPU, which the library
+ * holds until the process ends; descriptors and times reach it through kernel
+ * arguments, and nothing is synchronised (no event, no copy back): the call
+ * only enqueues work on opts->stream.
+ * Limits: 1..64 jobs, at most 8192 snapshot times over all jobs, and tallies
+ * that fit the array (about 4.1 million doubles of device tally blocks; the
+ * error message states the need).  opts->workspace must be NULL.
+ * Outputs (caller-owned device memory):
+ *   raw_out: each job's raw tally block (the doubles dmc_tally_read returns for
+ *     DMC_Q_RAW after dmc_simulate_batch), back to back in job order, raw_len
+ *     doubles available;
+ *   counters_out: optional, 6 per job: particles, scattering events, boundary
+ *     events, segments, capped, flights (the fields of dmc_stats);
+ *   raw_offsets: optional host array of n_jobs + 1 entries: job j's block is
+ *     raw_out[raw_offsets[j] .. raw_offsets[j + 1]).  With raw_out NULL the call
+ *     only validates the jobs and fills raw_offsets (no device work).
+ * Every call on a GPU shares that GPU's array and leaves its contents behind;
+ * each call clears what must start at zero.  Calls that overlap on one GPU (on
+ * different streams, or from several threads without ordering) race on it:
+ * serialise them.  Errors: DMC_E_INVALID (limits, raw_len or nscat_out_len too
+ * small), DMC_E_DEVICE. */
+dmc_status dmc_simulate_batch_noalloc(const dmc_job *jobs, int32_t n_jobs, const dmc_run_opts *opts, double *raw_out,
+                                      size_t raw_len, uint64_t *counters_out, size_t *raw_offsets);
+
 /* ---- Autotuner (persistent form) ----
  * Picks block size, queue chunk, refill threshold and tally privatisation for a
  * batch by timing trial launches of a sample of it.  The sample cuts every job

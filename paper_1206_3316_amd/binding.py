@@ -118,6 +118,8 @@ _SIGS = {
                      C.c_int32),
     "dmc_simulate_batch": ([C.POINTER(dmc_job), C.c_int32, C.POINTER(dmc_run_opts), C.POINTER(C.c_void_p)],
                            C.c_int32),
+    "dmc_simulate_batch_noalloc": ([C.POINTER(dmc_job), C.c_int32, C.POINTER(dmc_run_opts), C.c_void_p, C.c_size_t,
+                                    C.c_void_p, C.POINTER(C.c_size_t)], C.c_int32),
     "dmc_autotune": ([C.POINTER(dmc_job), C.c_int32, C.POINTER(dmc_run_opts), C.POINTER(dmc_tune_opts),
                       C.POINTER(dmc_run_opts)], C.c_int32),
     "dmc_plan_truncation": ([C.POINTER(dmc_job), C.POINTER(dmc_run_opts), C.POINTER(dmc_trunc_opts),
@@ -214,6 +216,10 @@ def dmc_simulate(material, geometry, source, n_particles, seed, tally, times, n_
 
 def dmc_simulate_batch(jobs, n_jobs, opts, out):
     return _call("dmc_simulate_batch", jobs, n_jobs, opts, out)
+
+
+def dmc_simulate_batch_noalloc(jobs, n_jobs, opts, raw_out, raw_len, counters_out, raw_offsets):
+    return _call("dmc_simulate_batch_noalloc", jobs, n_jobs, opts, raw_out, raw_len, counters_out, raw_offsets)
 
 
 def dmc_autotune(jobs, n_jobs, base, tune, best):
@@ -538,6 +544,47 @@ def simulate_one(job, material: Optional[Material] = None, precision="fp32", for
     dmc_simulate(j.material, j.geometry, C.byref(j.source), j.n_particles, j.seed, C.byref(j.tally), j.times,
                  j.n_times, C.byref(o), C.byref(h))
     return Result(h, [job], keep)
+
+
+def noalloc_offsets(jobs, material: Material):
+    """Offsets of each job's raw block in the output of simulate_noalloc (n_jobs + 1
+    entries; a validation-only call of the entry point)."""
+    keep: list = [material]
+    arr = (dmc_job * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = job_struct(j, material, keep)
+    offs = (C.c_size_t * (len(jobs) + 1))()
+    o = run_opts()
+    dmc_simulate_batch_noalloc(arr, len(jobs), C.byref(o), None, 0, None, offs)
+    return [int(x) for x in offs]
+
+
+def simulate_noalloc(jobs, raw_out, counters_out=None, material: Optional[Material] = None, precision="fp32",
+                     form="persistent", stream=None, nscat_out=None, **params):
+    """Enqueue ``jobs`` through dmc_simulate_batch_noalloc: raw tallies into the CUDA
+    float64 tensor ``raw_out`` (layout from noalloc_offsets), counters (6 per job,
+    dmc_stats order) into the optional CUDA int64 tensor ``counters_out``.
+    Asynchronous on ``stream``; returns the offsets."""
+    if not isinstance(jobs, (list, tuple)):
+        jobs = [jobs]
+    material = material or Material(jobs[0].material)
+    if not raw_out.is_cuda or raw_out.dtype.itemsize != 8 or not raw_out.is_floating_point() \
+            or not raw_out.is_contiguous():
+        raise ValueError("raw_out must be a contiguous CUDA float64 tensor")
+    if counters_out is not None and (not counters_out.is_cuda or counters_out.element_size() != 8
+                                     or counters_out.is_floating_point() or counters_out.numel() < 6 * len(jobs)):
+        raise ValueError("counters_out must be a CUDA 64-bit integer tensor of 6 entries per job")
+    keep: list = [material]
+    arr = (dmc_job * len(jobs))()
+    for i, j in enumerate(jobs):
+        arr[i] = job_struct(j, material, keep)
+    ns_ptr, ns_len = _nscat_buffer(nscat_out, sum(int(j.n_particles) for j in jobs))
+    o = run_opts(precision, form, getattr(stream, "cuda_stream", stream), nscat_out=ns_ptr, nscat_out_len=ns_len,
+                 **params)
+    offs = (C.c_size_t * (len(jobs) + 1))()
+    dmc_simulate_batch_noalloc(arr, len(jobs), C.byref(o), raw_out.data_ptr(), raw_out.numel(),
+                               counters_out.data_ptr() if counters_out is not None else None, offs)
+    return [int(x) for x in offs]
 
 
 TUNED_PARAMS = ("block", "chunk", "refill_min", "lds_tally")

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libdmc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["dmc_kernels.hip", "dmc_host.cpp", "dmc_server.cpp", "dmc_tune.cpp", "dmc_sched.cpp"]
+SOURCES = ["dmc_kernels.hip", "dmc_noalloc.hip", "dmc_host.cpp", "dmc_server.cpp", "dmc_tune.cpp", "dmc_sched.cpp"]
 
 # -ffp-contract=off: no FMA contraction, so the FP64 parity mode rounds like the
 # FP64 reference; packed FP32 ops are disabled; the CFG-sinking pass is turned
