@@ -440,10 +440,9 @@ int kernel_spec(const JobDev *jobs, int n_jobs)
 
 int launch_spec(const dmc_material *M, const JobDev *devs, int n_jobs)
 {
-    const int spec = kernel_spec(devs, n_jobs);
-    // the slab kernel follows the z direction cosine alone, which suffices for
-    // isotropic scattering only
-    return (spec == GEOM_SLAB && M->scatter_g != 0.0) ? (int)GEOM_ANY : spec;
+    // the specialised kernels scatter isotropically: another phase function takes
+    // the generic kernel
+    return M->scatter_g != 0.0 ? (int)GEOM_ANY : kernel_spec(devs, n_jobs);
 }
 
 dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const LaunchBuffers &b, const dmc_run_opts &o,

@@ -66,6 +66,25 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     return make_uint4(c0, c1, c2, c3);
 }
 
+// The same block with the key schedule given: rk[2 r], rk[2 r + 1] are the key
+// words of round r (kernels that keep every lane's schedule in vector registers:
+// a three-input xor with a vector operand issues faster than with a scalar one).
+__device__ __forceinline__ uint4 philox_rk(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, const uint32_t *rk)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, rk[2 * r], 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, rk[2 * r + 1], 0x96);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
 __device__ __forceinline__ uint32_t alias_draw(const uint32_t *tab, int bits, uint32_t w)
 {
     const uint32_t idx = w >> (32 - bits);
@@ -222,6 +241,7 @@ struct Lane {
     R rad2;  // pore radius squared (pore cells); kept in a register so the boundary
              // search of every flight does not wait on a load of the job descriptor
     uint32_t key0, key1;
+    uint32_t rk[20];        // key schedule of the STEP blocks (kernels with lane_round_keys)
     // tally addresses of this particle: bins of its batch (LDS index or, if
     // bl < 0, HBM offset) and the H_j block
     int32_t bl, hl;
@@ -373,6 +393,16 @@ __device__ __forceinline__ void scatter_hg(Lane<R> &p, const KArgs &a, uint32_t 
     p.oz = mu * nz + st * (c * t1z + s * t2z);
 }
 
+// Kernels that keep each lane's Philox key schedule in vector registers (20
+// words, computed when a particle is bound to the lane) instead of deriving it
+// per flight on the scalar unit from a wave-uniform key: the FP32 slab,
+// half-space and gradient kernels, which have the registers to spare.
+template <typename R, int G>
+__device__ constexpr bool lane_round_keys()
+{
+    return sizeof(R) == 4 && (G == GEOM_SLAB || G == GEOM_HALF || G == GEOM_GRAD);
+}
+
 // Per-particle copies of its job's parameters.
 template <typename R, int G>
 __device__ __forceinline__ void bind_job(Lane<R> &p, const JobDev &J, uint64_t pid, int job)
@@ -393,6 +423,13 @@ __device__ __forceinline__ void bind_job(Lane<R> &p, const JobDev &J, uint64_t p
     p.bw = (R)J.bin_width;
     p.key0 = J.key0;
     p.key1 = J.key1;
+    if constexpr (lane_round_keys<R, G>()) {
+#pragma unroll
+        for (int r = 0; r < 10; ++r) {
+            p.rk[2 * r] = J.key0 + (uint32_t)r * 0x9E3779B9u;
+            p.rk[2 * r + 1] = J.key1 + (uint32_t)r * 0xBB67AE85u;
+        }
+    }
     p.rzhi = (J.off_region >= 0 && (G == GEOM_HALF || G == GEOM_ANY)) ? (R)J.region_z[1] : -Pr<R>::inf();
     p.rwin = -1;
     p.rt = p.rq = 0.0;
@@ -1228,10 +1265,11 @@ __device__ __forceinline__ WaveKey wave_key_active(const Lane<R> &p)
 }
 
 // The STEP block of flight k.
-template <typename R>
+template <typename R, int G>
 __device__ __forceinline__ uint4 philox_step(const Lane<R> &p, const WaveKey &wk, uint32_t k)
 {
     const uint32_t c0 = (uint32_t)p.pid, c1 = (uint32_t)(p.pid >> 32);
+    if constexpr (lane_round_keys<R, G>()) return philox_rk(c0, c1, k, TAG_STEP, p.rk);
     if (wk.uniform) return philox(c0, c1, k, TAG_STEP, wk.k0, wk.k1);
     return philox(c0, c1, k, TAG_STEP, p.key0, p.key1);
 }
@@ -1250,7 +1288,7 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
 {
     constexpr bool PER = has_periodic<G>();
     const bool cont = PER && p.rem >= (R)0;
-    const uint4 w = philox_step(p, wk, cont ? p.k - 1u : p.k);
+    const uint4 w = philox_step<R, G>(p, wk, cont ? p.k - 1u : p.k);
     R dt;
     if (cont) {
         dt = p.rem;
@@ -1314,9 +1352,10 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
         } else {                                                          // step IVb
             const uint32_t m = alias_draw(sh.gain, a.gain_bits, w.y);
             load_state(p, a, sh, m);
-            // the slab kernel runs isotropic scattering only (it tracks the z direction
-            // cosine alone); launches with another phase function take the generic kernel
-            if (G == GEOM_SLAB || a.scatter_g == 0.0)
+            // the specialised kernels scatter isotropically (the slab kernel tracks the
+            // z direction cosine alone); launches with another phase function take the
+            // generic kernel
+            if (G != GEOM_ANY || a.scatter_g == 0.0)
                 isotropic(p, w.z, w.w);
             else
                 scatter_hg(p, a, w.z, w.w);

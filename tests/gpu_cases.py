@@ -57,8 +57,8 @@ def parity_cases():
         "periodic_film": periodic_slab(),
         "spot": small_spot(),
         "spot_region": spot_region(),
-        # Henyey-Greenstein scattering (the generalisation of step IVb): the slab takes the
-        # generic kernel, the pore cell the gradient kernel, the spot the half-space kernel
+        # Henyey-Greenstein scattering (the generalisation of step IVb): every launch of such a
+        # material takes the generic kernel
         "slab_hg": di.slab_job(di.gray_material(scatter_g=-0.4), 150e-9, 20_000, seed=110, n_bins=12),
         "pore_cell_hg": di.pore_cell(100e-9, 0.3, 20_000, seed=109, material=di.silicon_like(scatter_g=0.6),
                                      kmax=40, n_hj=10),
