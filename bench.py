@@ -42,6 +42,13 @@ sys.path.insert(0, ROOT)
 # cheapest form of each step found so far: a kernel change that removes work
 # from the minimum lowers them, so the fraction does not flatter an older,
 # costlier kernel.
+def philox_cost(c):
+    """A Philox4x32-10 block in the cheaper of its two measured forms: the key
+    schedule in scalar registers, or held per lane in vector registers (the
+    trajectory kernels' form)."""
+    return min(c["philox_uniform_key"], c["philox_lane_key"])
+
+
 def slab_items(c):
     """One flight of the cross-plane slab path (persistent FP32 slab kernel).
     The start bin of a segment is the end bin of the previous one, so one bin
@@ -49,7 +56,7 @@ def slab_items(c):
     only on a trajectory's end points, so it costs nothing per flight; a slab
     needs only the z direction cosine after a scattering event (no azimuth)."""
     return [
-        ("Philox4x32-10 block", c["philox_uniform_key"]),
+        ("Philox4x32-10 block", philox_cost(c)),
         ("uniform u for the flight (funnel shift, subtract)", 2),
         ("mu = 2u - 1 from a second word (funnel shift, FMA, add)", 3),
         ("flight time -tau ln2 log2 u: log2, one multiply", c["log"] + 1),
@@ -70,7 +77,7 @@ def half_items(c):
     2744 flights) costs a cell index (3 axes: subtract, scale, floor, convert, 2
     compares) and one FP64 atomic, about 25 slots, i.e. 0.46 per flight."""
     return [
-        ("Philox4x32-10 block", c["philox_uniform_key"]),
+        ("Philox4x32-10 block", philox_cost(c)),
         ("flight time: uniform (2), log2, one multiply", 3 + c["log"]),
         ("surface distance through the reciprocal of v Omega_z, hit test, select", 4 + c["rcp"]),
         ("segment end time t + seg in FP64 (convert, add), next-sample and final-time compares",
@@ -101,7 +108,7 @@ def grad_unit_costs(c):
                   + 3 + 2 * c["f64_add"]  # s v Omega_z seg to FP64, added to L_z and H_j
                   + 3)  # segment counter, cap test, continuation test
     return {
-        "flight": c["philox_uniform_key"] + 3 + c["log"],
+        "flight": philox_cost(c) + 3 + c["log"],
         "segment_film": search_film + seg_common,
         "segment_pore": search_pore + seg_common,
         "scatter": 6 + 8 + c["sin"] + c["cos"] + c["sqrt"] + 1 + 2 * c["f64_add"],  # alias, isotropic, H_j flush
@@ -133,7 +140,7 @@ def op_costs(b):
 # WRITE_SIZE runs (profiles/), scaled by the same counters' reading for a plain
 # device copy of known size (bench.py --copy-probe); valid only for the kernel
 # source it was measured on.
-TRAFFIC = {"kernel_sha1": "beb9bf16be071456637116016faa292036a56a69", "bytes": 54553312}  # profiles/persistent_kernel_slab_12films_counters.md
+TRAFFIC = {"kernel_sha1": "a96ac799d7cc4d28c0d0f79d765f610f700daa36", "bytes": 54577213}  # profiles/persistent_kernel_slab_12films_counters.md
 CU, LANES_PER_CU_CLK, CLOCK = 256, 64, 2.4e9
 PEAK_LANE_OPS = CU * LANES_PER_CU_CLK * CLOCK  # 3.93e13 full-rate VALU lane-ops/s
 
