@@ -149,9 +149,18 @@ def test_fp64_parity_with_many_periodic_hops(name, oracle_runs):
 
 # ----------------------------------------------- production FP32 tolerance ----
 
+# Pore cells are chaotic billiards: their FP32 and FP64 trajectories separate, so
+# there the two forms agree statistically only.  Everywhere else the two forms
+# draw the same random numbers and follow the same paths unless rounding flips a
+# decision, and the FP32 error must also stay below 1e-3 of the quantity's scale
+# (observed: at most 3.5e-4).
+CHAOTIC = {"pore_cell", "pore_cell_specular", "pore_field", "pore_cell_hg"}
+
+
 def _assert_stat_close(name, q, got, got_se, ref, ref_se, scale=None, rel=1e-3):
     """|got - ref| <= max(3 combined standard errors, rel * scale); scale defaults to
-    the largest |ref| of the quantity (per-quantity relative error)."""
+    the largest |ref| of the quantity (per-quantity relative error).  Outside the
+    chaotic cases also |got - ref| <= rel * scale (the same realisation)."""
     got, ref = np.atleast_1d(got), np.atleast_1d(ref)
     comb = np.sqrt(np.atleast_1d(got_se) ** 2 + np.atleast_1d(ref_se) ** 2)
     sc = float(np.abs(ref).max()) if scale is None else scale
@@ -164,6 +173,8 @@ def _assert_stat_close(name, q, got, got_se, ref, ref_se, scale=None, rel=1e-3):
           f"max |diff| / combined SE = {in_se.max():.2f} over {diff.shape[0]} values", flush=True)
     bad = diff > tol
     assert not bad.any(), (name, q, got[bad], ref[bad], tol[bad])
+    if name not in CHAOTIC:
+        assert float(diff.max()) <= rel * sc, (name, q, float(diff.max()) / sc)
 
 
 @pytest.mark.parametrize("name", list(CASES))
