@@ -492,6 +492,8 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
                      : o.prio_flights < 0            ? 0u
                                                      : (uint32_t)std::min<int32_t>(o.prio_flights, 1 << 27);
     a.total += b.n_resume;
+    for (int i = 0; i < n_jobs; ++i)
+        if (devs[i].off_region >= 0) a.any_region = 1;
     if ((b.drain_iters || b.n_resume) && o.form != DMC_FORM_PERSISTENT)
         return fail(DMC_E_INVALID, "time-bounded launches need the persistent form");
     if (b.n_resume && !b.drain_iters) return fail(DMC_E_INVALID, "resuming needs a time-bounded launch");

@@ -90,7 +90,8 @@ struct KArgs {
     uint64_t qbegin;                // plain form: first queue index of this launch
     uint64_t total;                 // one past the last queue index of this launch
     unsigned long long *queue;      // next queue index (persistent form)
-    int32_t gain_bits, flux_bits, init_bits, pad0;
+    int32_t gain_bits, flux_bits, init_bits;
+    int32_t any_region;             // 1: some job of the launch has a windowed region tally
     const uint32_t *gain_packed, *flux_packed, *init_packed;
     const float4 *st32;             // per state: v, tau, 1/tau, 0
     const double2 *st64;            // per state: v, tau

@@ -746,18 +746,20 @@ template <typename R>
 __device__ __forceinline__ void snapshot_add(const Lane<R> &p, const KArgs &a, const JobDev &J, int32_t ti, R x, R y,
                                              R z, double dt)
 {
-    int64_t idx[3];
+    int32_t idx[3];  // each below grid[d], an int32
     bool inside = true;
     if constexpr (sizeof(R) == 4) {
-        // production: the cell in FP32 with a precomputed scale (no divisions)
+        // production: the cell in FP32 with a precomputed scale (no divisions),
+        // the three axes without branches (the grid is read once)
         const float pos[3] = {x, y, z};
+        const float lo[3] = {J.grid_lof[0], J.grid_lof[1], J.grid_lof[2]};
+        const float sc[3] = {J.grid_scf[0], J.grid_scf[1], J.grid_scf[2]};
+        const float gn[3] = {(float)J.grid[0], (float)J.grid[1], (float)J.grid[2]};
+#pragma unroll
         for (int d = 0; d < 3; ++d) {
-            const float fl = floorf((pos[d] - J.grid_lof[d]) * J.grid_scf[d]);
-            if (!(fl >= 0.0f && fl < (float)J.grid[d])) {
-                inside = false;
-                break;
-            }
-            idx[d] = (int64_t)fl;
+            const float fl = floorf((pos[d] - lo[d]) * sc[d]);
+            inside = inside && fl >= 0.0f && fl < gn[d];
+            idx[d] = (int32_t)fminf(fmaxf(fl, 0.0f), gn[d]);  // clamped: a defined conversion
         }
     } else {
         // parity: the FP64 reference's operations
@@ -770,10 +772,11 @@ __device__ __forceinline__ void snapshot_add(const Lane<R> &p, const KArgs &a, c
                 inside = false;
                 break;
             }
-            idx[d] = (int64_t)fl;
+            idx[d] = (int32_t)fl;
         }
     }
-    const int64_t cell = inside ? (idx[2] * J.grid[1] + idx[1]) * J.grid[0] + idx[0] : J.ncell;
+    const int64_t cell =
+        inside ? ((int64_t)idx[2] * J.grid[1] + idx[1]) * (int64_t)J.grid[0] + idx[0] : J.ncell;
     const int64_t o = (int64_t)ti * (J.ncell + 1) + cell;
     gadd(a.tally + J.off_snap + o, (double)p.s);
     if (J.snap_abs_on) gadd(a.tally + J.off_snap_abs + o, 1.0);
@@ -1278,27 +1281,34 @@ __device__ __forceinline__ uint4 philox_step(const Lane<R> &p, const WaveKey &wk
 // One iteration of steps II-VI.  Returns 0 if the particle goes on, 1 if it
 // ended, 2 if it hit the flight cap.  A free flight that reaches a periodic face
 // continues from the opposite face with the time it has left and the words of
-// the block drawn when it began; in the gradient kernel such a continuation runs
-// in the same call for up to `hops` segments (waves with few live lanes pass a
-// large budget, so a lone long flight does not pay a whole iteration per face),
-// else in the next.
+// the block drawn when it began.  In the gradient kernel one call runs up to
+// `hops` segments of the particle, periodic continuations and new free flights
+// alike (waves with few live lanes, or holding a long-running particle, pass a
+// budget above one, so a long trajectory does not pay a whole iteration of its
+// wave per segment); elsewhere one segment.
 template <typename R, int FORM, int G>
 __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, const WaveKey &wk,
                                     uint32_t hops)
 {
     constexpr bool PER = has_periodic<G>();
-    const bool cont = PER && p.rem >= (R)0;
-    const uint4 w = philox_step<R, G>(p, wk, cont ? p.k - 1u : p.k);
-    R dt;
-    if (cont) {
-        dt = p.rem;
-    } else {
-        ++p.k;
-        dt = Pr<R>::flight(sizeof(R) == 4 ? p.ntl : p.tau, w.x);  // step II
-    }
     const int geom = (G == GEOM_ANY || G == GEOM_GRAD) ? p.geom : G;
     const bool gradient = (G == GEOM_GRAD) || ((G == GEOM_ANY) && (p.src == SRC_GRADIENT));
+    uint4 w;
+    R dt;
+    bool carried = false;  // a periodic continuation in this call: the block of its flight is at hand
     for (uint32_t hop = 1;; ++hop) {
+        if (carried) {
+            dt = p.rem;
+        } else {
+            const bool cont = PER && p.rem >= (R)0;
+            w = philox_step<R, G>(p, wk, cont ? p.k - 1u : p.k);
+            if (cont) {
+                dt = p.rem;
+            } else {
+                ++p.k;
+                dt = Pr<R>::flight(sizeof(R) == 4 ? p.ntl : p.tau, w.x);  // step II
+            }
+        }
         if (PER) {
             p.rem = (R)-1;
             ++p.nseg;
@@ -1320,8 +1330,9 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
         if (G == GEOM_ANY || G == GEOM_HALF) {
             const double tb_abs = p.t + (double)seg;
             if (p.tnext < tb_abs) score_snapshots<R, defer_snapshots<R, FORM, G>()>(p, a, J, (double)seg);
-            // windowed region tally; most segments lie wholly above the region
-            if (fmin(p.z, p.z + p.v * p.oz * seg) < p.rzhi) score_region(p, a, sh, J, seg);
+            // windowed region tally (a launch-wide flag skips the test when no job
+            // has one); most segments lie wholly above the region
+            if (a.any_region && fmin(p.z, p.z + p.v * p.oz * seg) < p.rzhi) score_region(p, a, sh, J, seg);
             if (tb_abs > p.tend) return 1;  // step VI
         }
         // move
@@ -1371,8 +1382,8 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
         if (segments<R, G>(p) >= a.iter_cap) return 2;
         // the generic kernel continues in the next iteration (registers are
         // scarcer there)
-        if (!(G == GEOM_GRAD && p.rem >= (R)0 && hop < hops)) return 0;
-        dt = p.rem;
+        if (!(G == GEOM_GRAD && hop < hops)) return 0;
+        carried = p.rem >= (R)0;
     }
 }
 
@@ -1534,7 +1545,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
     uint32_t pool_left = 0;
     bool qdry = false;  // the global queue has handed out every index (wave-uniform)
     uint32_t drain = 0, poll = 0, iter = 0;
-    uint32_t old_hops = 1;  // periodic-face budget of a wave holding a long-running particle
+    uint32_t old_hops = 1;  // segment budget of a wave holding a long-running particle
     WaveKey wk{0u, 0u, false};
     const uint64_t wave_lanes = __ballot(true);
     for (;;) {
@@ -1640,8 +1651,8 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
             else
                 __builtin_amdgcn_s_setprio(0);
             if constexpr (G == GEOM_GRAD) {
-                // a wave holding a long-running particle also lets its flights
-                // cross several periodic faces per iteration (8 from t1 / 16
+                // a wave holding a long-running particle also runs several
+                // segments of each particle per iteration (8 from t1 / 16
                 // segments on, 32 from t1, 64 from 16 t1), so the longest
                 // trajectories do not pace the launch
                 old_hops = __ballot(alive && age >= 16u * t1) ? 64u
@@ -1649,8 +1660,8 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                          : __ballot(alive && age >= t1 / 16u) ? 8u : 1u;
             }
         }
-        // a wave down to a few live lanes (the tail of a launch) lets a flight
-        // cross up to 64 periodic faces per iteration; a wave holding a
+        // a wave down to a few live lanes (the tail of a launch) runs up to 64
+        // segments of each particle per iteration; a wave holding a
         // long-running particle, the budget graded by its age
         const uint32_t hops = (G == GEOM_GRAD && __popcll(wave_lanes & ~need) <= 4) ? 64u : old_hops;
         if (alive) {
@@ -1665,9 +1676,18 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
             }
         }
         if (defer_snapshots<R, PF, G>()) {
-            // score the recorded crossings together once a quarter of the wave has one
-            if (__popcll(__ballot(alive && p.pend >= 0)) >= 16 && alive && p.pend >= 0)
-                snapshot_commit(p, a, a.jobs[p.job]);
+            // score the recorded crossings together once a quarter of the wave has one;
+            // when those lanes share one job its fields are read through the scalar unit
+            const bool mine = alive && p.pend >= 0;
+            const uint64_t cm = __ballot(mine);
+            if (__popcll(cm) >= 16) {
+                const int jw = __builtin_amdgcn_readlane(p.job, __ffsll((unsigned long long)cm) - 1);
+                if (__ballot(mine && p.job != jw) == 0ull) {
+                    if (mine) snapshot_commit(p, a, a.jobs[jw]);
+                } else if (mine) {
+                    snapshot_commit(p, a, a.jobs[p.job]);
+                }
+            }
         }
     }
     if (ended) finish<R, PF, G>(p, a, sh, a.jobs[p.job], ended == 2);
