@@ -1546,6 +1546,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
     bool qdry = false;  // the global queue has handed out every index (wave-uniform)
     uint32_t drain = 0, poll = 0, iter = 0;
     uint32_t old_hops = 1;  // segment budget of a wave holding a long-running particle
+    bool hold = false;      // the wave holds a very long trajectory: its free lanes are not refilled
     WaveKey wk{0u, 0u, false};
     const uint64_t wave_lanes = __ballot(true);
     for (;;) {
@@ -1555,7 +1556,8 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
         uint64_t need = __ballot(!alive);
         const int n_free = __popcll(need);
         const bool have_work = pool_left > 0u || !qdry;
-        if (n_free > 0 && have_work && (n_free >= a.refill_min || n_free == 64)) {
+        if (G == GEOM_GRAD && n_free == 64) hold = false;
+        if (n_free > 0 && have_work && !hold && (n_free >= a.refill_min || n_free == 64)) {
             if (ended) {
                 finish<R, PF, G>(p, a, sh, a.jobs[p.job], ended == 2);
                 ended = 0;
@@ -1658,6 +1660,11 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                 old_hops = __ballot(alive && age >= 16u * t1) ? 64u
                          : __ballot(alive && age >= t1) ? 32u
                          : __ballot(alive && age >= t1 / 16u) ? 8u : 1u;
+                // from t1 segments on, the wave stops refilling: its other lanes end
+                // their particles, and the long one runs alone at the full budget
+                // below, no longer paced by their divergent paths (one wave of the
+                // thousands in a launch gives up its other lanes for it)
+                hold = old_hops >= 32u;
             }
         }
         // a wave down to a few live lanes (the tail of a launch) runs up to 64
