@@ -475,7 +475,12 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
     set_times(p, a, J);
 
     const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
-    const uint4 A = philox(plo, phi, 0u, TAG_EMIT_A, p.key0, p.key1);
+    // the emission blocks, with the lane's key schedule where the kernel keeps one
+    auto emit_block = [&](uint32_t c2, uint32_t tag) {
+        if constexpr (lane_round_keys<R, G>()) return philox_rk(plo, phi, c2, tag, p.rk);
+        return philox(plo, phi, c2, tag, p.key0, p.key1);
+    };
+    const uint4 A = emit_block(0u, TAG_EMIT_A);
     uint32_t m;
     const int src = (G == GEOM_SLAB)   ? (int)SRC_WALLS
                     : (G == GEOM_HALF) ? (int)SRC_GAUSSIAN
@@ -496,7 +501,7 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
         p.s = (R)J.wall_sign[wall];
         if (J.disp_tel && wall == 1 && axis == 2) tadd(a, sh, J.lds_dispx, J.off_dispx, p.batch, -(double)p.s);
     } else if (src == SRC_GAUSSIAN) {
-        const uint4 B = philox(plo, phi, 0u, TAG_EMIT_B, p.key0, p.key1);
+        const uint4 B = emit_block(0u, TAG_EMIT_B);
         m = alias_draw(a.init_packed, a.init_bits, A.y);
         isotropic(p, A.z, A.w);
         const R sigma = (R)J.sigma;
@@ -511,7 +516,7 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
         p.z = fabs(sigma * rz * c2);
         p.s = (R)J.sign0;
     } else {  // gradient source, Eq. (6)
-        const uint4 B = philox(plo, phi, 0u, TAG_EMIT_B, p.key0, p.key1);
+        const uint4 B = emit_block(0u, TAG_EMIT_B);
         m = alias_draw(a.flux_packed, a.flux_bits, A.y);
         const R sz = (B.w >> 31) ? (R)-1 : (R)1;
         lambertian_plane(p, 2, sz, A.z, A.w);
@@ -523,7 +528,7 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
             const R r2 = p.rad2;
             bool ok = false;
             for (uint32_t att = 0; att < (uint32_t)kPosAttempts && !ok; ++att) {
-                const uint4 Bb = (att == 0) ? B : philox(plo, phi, att, TAG_EMIT_B, p.key0, p.key1);
+                const uint4 Bb = (att == 0) ? B : emit_block(att, TAG_EMIT_B);
                 const R x = p.len * Pr<R>::u(Bb.x), z = p.len * Pr<R>::u(Bb.y);
                 if ((x - c) * (x - c) + (z - c) * (z - c) > r2) {
                     p.x = x;
