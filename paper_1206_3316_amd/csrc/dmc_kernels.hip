@@ -1287,10 +1287,11 @@ __device__ __forceinline__ uint4 philox_step(const Lane<R> &p, const WaveKey &wk
 // ended, 2 if it hit the flight cap.  A free flight that reaches a periodic face
 // continues from the opposite face with the time it has left and the words of
 // the block drawn when it began.  In the gradient kernel one call runs up to
-// `hops` segments of the particle, periodic continuations and new free flights
-// alike (waves with few live lanes, or holding a long-running particle, pass a
-// budget above one, so a long trajectory does not pay a whole iteration of its
-// wave per segment); elsewhere one segment.
+// `hops` segments of the particle: periodic continuations under any budget above
+// one (waves holding a long-running particle), new free flights as well under
+// the full budget of 64 (waves down to a few live lanes, where no other lane
+// waits on the loop), so a long trajectory does not pay a whole iteration of its
+// wave per segment; elsewhere one segment.
 template <typename R, int FORM, int G>
 __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, const WaveKey &wk,
                                     uint32_t hops)
@@ -1387,8 +1388,10 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
         if (segments<R, G>(p) >= a.iter_cap) return 2;
         // the generic kernel continues in the next iteration (registers are
         // scarcer there)
-        if (!(G == GEOM_GRAD && hop < hops)) return 0;
+        // periodic continuations within the budget; new free flights too at the
+        // full budget (a wave down to a few live lanes), where no other lane waits
         carried = p.rem >= (R)0;
+        if (!(G == GEOM_GRAD && hop < hops && (carried || hops >= 64u))) return 0;
     }
 }
 
