@@ -1010,46 +1010,37 @@ __device__ __forceinline__ R search(const Lane<R> &p, const JobDev &J, int geom,
         best = ok ? Pr<R>::div((R)0 - p.z, w) : best;
         surf = ok ? 0 : kNoSurface;
     } else {  // pore cell: faces 0: x=0, 1: x=P, 2: z=0, 3: z=P, 4: pore surface
+        // every candidate is evaluated and kept by selects, without branches (the
+        // lanes of a wave differ in the signs of their speeds and in what they hit)
 #pragma unroll
         for (int f = 0; f < 2; ++f) {
+            // one face per axis, chosen by the sign of the speed along it
             const R c = (f == 0) ? p.x : p.z;
             const R w = p.v * ((f == 0) ? p.ox : p.oz);
-            R t = Pr<R>::inf();
-            int32_t id = kNoSurface;
-            if (w > (R)0 && p.last != 2 * f + 1) {
-                t = Pr<R>::div(p.len - c, w);
-                id = 2 * f + 1;
-            } else if (w < (R)0 && p.last != 2 * f) {
-                t = Pr<R>::div((R)0 - c, w);
-                id = 2 * f;
-            }
-            if (t < best) {
-                best = t;
-                surf = id;
-            }
+            const bool up = w > (R)0;
+            const int32_t id = up ? 2 * f + 1 : 2 * f;
+            const bool ok = (up || w < (R)0) && p.last != id;
+            const R t = Pr<R>::div(up ? p.len - c : (R)0 - c, w);
+            const bool take = ok && t < best;
+            best = take ? t : best;
+            surf = take ? id : surf;
         }
+        // the pore: the entry root of |x - c|^2 = r^2 along the flight in x-z (a
+        // particle found inside, moving inward, meets it at once)
         const R r2 = p.rad2;
-        if (r2 > (R)0 && p.last != 4) {
-            const R c = (R)0.5 * p.len;
-            const R dx = p.x - c, dz = p.z - c;
-            const R aq = p.ox * p.ox + p.oz * p.oz;
-            const R bq = dx * p.ox + dz * p.oz;
-            const R cq = dx * dx + dz * dz - r2;
-            if (aq > (R)0 && bq < (R)0) {
-                R dist = Pr<R>::inf();
-                if (cq <= (R)0)
-                    dist = (R)0;
-                else {
-                    const R disc = bq * bq - aq * cq;
-                    if (disc > (R)0) dist = Pr<R>::div(-bq - Pr<R>::sq(disc), aq);
-                }
-                const R t = Pr<R>::div(dist, p.v);
-                if (t < best) {
-                    best = t;
-                    surf = 4;
-                }
-            }
-        }
+        const R c = (R)0.5 * p.len;
+        const R dx = p.x - c, dz = p.z - c;
+        const R aq = p.ox * p.ox + p.oz * p.oz;
+        const R bq = dx * p.ox + dz * p.oz;
+        const R cq = dx * dx + dz * dz - r2;
+        const R disc = bq * bq - aq * cq;
+        const bool inside = cq <= (R)0;
+        const bool ok = r2 > (R)0 && p.last != 4 && aq > (R)0 && bq < (R)0 && (inside || disc > (R)0);
+        const R dist = inside ? (R)0 : Pr<R>::div(-bq - Pr<R>::sq(disc > (R)0 ? disc : (R)0), aq);
+        const R t = Pr<R>::div(dist, p.v);
+        const bool take = ok && t < best;
+        best = take ? t : best;
+        surf = take ? (int32_t)4 : surf;
     }
     return Pr<R>::nonneg(best);
 }
@@ -1564,8 +1555,9 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
         uint64_t need = __ballot(!alive);
         const int n_free = __popcll(need);
         const bool have_work = pool_left > 0u || !qdry;
-        if (G == GEOM_GRAD && n_free == 64) hold = false;
-        if (n_free > 0 && have_work && !hold && (n_free >= a.refill_min || n_free == 64)) {
+        constexpr bool HOLD = G == GEOM_GRAD && !BOUNDED;  // not in time-bounded launches (registers)
+        if (HOLD && n_free == 64) hold = false;
+        if (n_free > 0 && have_work && !(HOLD && hold) && (n_free >= a.refill_min || n_free == 64)) {
             if (ended) {
                 finish<R, PF, G>(p, a, sh, a.jobs[p.job], ended == 2);
                 ended = 0;
