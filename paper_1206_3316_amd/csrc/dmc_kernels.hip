@@ -921,12 +921,15 @@ __device__ __forceinline__ void region_flush(Lane<R> &p, const KArgs &a, const S
 template <typename R>
 __device__ void score_region(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, R seg)
 {
+    // the region's bounds, read together (one wait for all of them)
+    const R zlo = (R)J.region_z[0], zhi = (R)J.region_z[1];
+    const R cx = (R)J.region_c[0], cy = (R)J.region_c[1], rr = (R)J.region_r;
     R lo = (R)0, hi = seg;
     const R wz = p.v * p.oz;
     if (wz == (R)0) {
-        if (!(p.z >= (R)J.region_z[0] && p.z < (R)J.region_z[1])) return;
+        if (!(p.z >= zlo && p.z < zhi)) return;
     } else {
-        R ta = Pr<R>::div((R)J.region_z[0] - p.z, wz), tb = Pr<R>::div((R)J.region_z[1] - p.z, wz);
+        R ta = Pr<R>::div(zlo - p.z, wz), tb = Pr<R>::div(zhi - p.z, wz);
         if (ta > tb) {
             const R s = ta;
             ta = tb;
@@ -936,8 +939,7 @@ __device__ void score_region(Lane<R> &p, const KArgs &a, const Shared &sh, const
         if (tb < hi) hi = tb;
     }
     const R wx = p.v * p.ox, wy = p.v * p.oy;
-    const R dx = p.x - (R)J.region_c[0], dy = p.y - (R)J.region_c[1];
-    const R rr = (R)J.region_r;
+    const R dx = p.x - cx, dy = p.y - cy;
     const R A = wx * wx + wy * wy, B = dx * wx + dy * wy, Cc = dx * dx + dy * dy - rr * rr;
     bool within = false;
     if constexpr (sizeof(R) == 4) {
