@@ -132,9 +132,12 @@ def test_fp64_parity_with_oracle(name, form, oracle_runs):
 
 @pytest.mark.parametrize("name", ["pore_cell", "pore_cell_specular", "pore_field", "periodic_film"])
 def test_fp64_parity_with_many_periodic_hops(name, oracle_runs):
-    """A tiny priority threshold makes the gradient kernel cross up to 64
-    periodic faces per iteration in nearly every wave: the grouping of segments
-    into iterations must not change the realisation (same oracle bar)."""
+    """A tiny priority threshold makes nearly every wave of the gradient kernel
+    run several segments per call (periodic faces; new flights too once a wave
+    is down to a few lanes) and stop refilling its free lanes while it holds a
+    particle past the threshold: neither the grouping of segments into
+    iterations nor the refill order may change the realisation (same oracle
+    bar)."""
     job = CASES[name]
     prep, oraw, ocnt, ons, _ = oracle_runs(name)
     print(f"case {name} persistent prio_flights 16 n {job.n_particles}", flush=True)
