@@ -253,6 +253,7 @@ struct Lane {
     double c0, c1, c2;      // entry A: the bin the particle is in
     double d0, d1, d2;      // entry B: the bin it came from
     int32_t tcur;           // index of the next snapshot time
+    int32_t toff;           // the job's first sample time in KArgs::times (half-space kernel)
     double tnext, tend;     // next snapshot time and final time (+inf when steady)
     int32_t pend;           // deferred snapshot crossing: time index (-1: none) and position
     R px, py, pz;
@@ -434,6 +435,7 @@ __device__ __forceinline__ void bind_job(Lane<R> &p, const JobDev &J, uint64_t p
     p.rwin = -1;
     p.rt = p.rq = 0.0;
     p.pend = -1;
+    if constexpr (G == GEOM_HALF) p.toff = J.times_off;
     p.fld = (G == GEOM_GRAD || G == GEOM_ANY) ? (J.off_field >= 0 ? 1 : 0) : 0;
     {
         const int32_t boff = p.batch * 3 * p.n_bins;
@@ -806,7 +808,8 @@ template <typename R, bool DEFER>
 __device__ void score_snapshots(Lane<R> &p, const KArgs &a, const JobDev &J, double seg)
 {
     const double ta = p.t, tb = p.t + seg;
-    const double *times = a.times + J.times_off;
+    // the production kernel keeps the job's offset in the lane (one load fewer in turn)
+    const double *times = a.times + (DEFER ? p.toff : J.times_off);
     while (p.tnext < tb) {
         const double tj = p.tnext;
         if (tj >= ta) {
