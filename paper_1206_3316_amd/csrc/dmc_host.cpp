@@ -448,7 +448,14 @@ int launch_spec(const dmc_material *M, const JobDev *devs, int n_jobs)
 dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const LaunchBuffers &b, const dmc_run_opts &o,
                        LaunchPlan &plan)
 {
-    const int spec = launch_spec(M, devs, n_jobs);
+    int spec = launch_spec(M, devs, n_jobs);
+    // the persistent half-space kernel (not time-bounded) reads the sample times
+    // from LDS: all of the launch's times must fit, else the generic kernel runs
+    int32_t n_times_all = 0;
+    for (int i = 0; i < n_jobs; ++i) n_times_all = std::max(n_times_all, devs[i].times_off + devs[i].n_times);
+    const bool bounded_launch = b.drain_iters > 0 || b.n_resume > 0;
+    const bool times_lds = spec == GEOM_HALF && o.form == DMC_FORM_PERSISTENT && !bounded_launch;
+    if (times_lds && n_times_all > kLdsTimes) spec = GEOM_ANY;
     KArgs a{};
     {
         const double g = M->scatter_g;
@@ -498,6 +505,8 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
         return fail(DMC_E_INVALID, "time-bounded launches need the persistent form");
     if (b.n_resume && !b.drain_iters) return fail(DMC_E_INVALID, "resuming needs a time-bounded launch");
     const size_t stats_lds = a.lds_stats ? (size_t)n_jobs * kStats * 8 : 0;
+    a.times_lds = (spec == GEOM_HALF && times_lds) ? n_times_all : 0;
+    const size_t times_bytes = (size_t)a.times_lds * 8;
     for (int i = 0; i < n_jobs; ++i) {
         JobDev &d = devs[i];
         d.lds_bins = d.lds_kappa = d.lds_hj = d.lds_dispx = d.lds_region = d.lds_field = -1;
@@ -509,9 +518,9 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
         // LDS: gain table + per-state data, then privatised tallies while they fit
         const size_t tab = (((size_t)a.kpad * 4 + 15) & ~size_t(15)) + (size_t)M->K * 16;
         const size_t cap = (size_t)max_lds_bytes();
-        if (tab + stats_lds + 1024 > cap)
+        if (tab + stats_lds + times_bytes + 1024 > cap)
             return fail(DMC_E_UNSUPPORTED, "persistent form: material tables do not fit in LDS");
-        const size_t budget = (cap - tab - stats_lds - 16) / 8;  // doubles
+        const size_t budget = (cap - tab - stats_lds - times_bytes - 16) / 8;  // doubles
         int32_t lo = 0;
         if (o.lds_tally) {
             for (int i = 0; i < n_jobs; ++i) {
@@ -555,12 +564,11 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
         a.bins_lds_all = 1;
         for (int i = 0; i < n_jobs; ++i)
             if (devs[i].off_bins >= 0 && devs[i].lds_bins < 0) a.bins_lds_all = 0;
-        lds_bytes = ((tab + 15) & ~size_t(15)) + (size_t)lo * 8 + stats_lds;
+        lds_bytes = ((tab + 15) & ~size_t(15)) + (size_t)lo * 8 + stats_lds + times_bytes;
         a.chunk = o.chunk > 0 ? o.chunk : 1024;
         a.refill_min = o.refill_min > 0 ? o.refill_min : 16;
         block = o.block > 0 ? o.block : (lds_bytes > 64 * 1024 ? 1024 : 512);
-        const bool bounded = b.drain_iters > 0 || b.n_resume > 0;
-        const int per_cu = occupancy_blocks(o.precision, o.form, spec, bounded, block, lds_bytes);
+        const int per_cu = occupancy_blocks(o.precision, o.form, spec, bounded_launch, block, lds_bytes);
         grid = o.grid_blocks > 0 ? o.grid_blocks : device_cus() * per_cu;
         if (b.drain_iters) {
             // every lane may suspend one particle and every wave the unstarted rest of

@@ -272,7 +272,24 @@ struct Shared {
     const void *st;              // per-state data: LDS (persistent) or global (plain)
     double *ltally;              // LDS tallies (slots used only where a job's lds offset >= 0)
     unsigned long long *lstats;  // LDS per-job counters (used only if KArgs::lds_stats)
+    double *ltimes;              // LDS copy of the launch's sample times (persistent half-space kernel)
 };
+
+// The persistent half-space kernel reads the sample times from their LDS copy
+// (the host sizes LDS for them, or runs the generic kernel); the others read
+// KArgs::times.
+template <int FORM, int G>
+__device__ constexpr bool times_in_lds()
+{
+    return FORM == FORM_PERSISTENT && G == GEOM_HALF;
+}
+
+template <int FORM, int G>
+__device__ __forceinline__ const double *times_of(const KArgs &a, const Shared &sh)
+{
+    if constexpr (times_in_lds<FORM, G>()) return sh.ltimes;
+    return a.times;
+}
 
 template <typename R>
 __device__ __forceinline__ void load_state(Lane<R> &p, const KArgs &a, const Shared &sh, uint32_t m);
@@ -450,15 +467,15 @@ __device__ __forceinline__ void bind_job(Lane<R> &p, const JobDev &J, uint64_t p
 }
 
 // Keeps the next snapshot time and the final time in registers.
-template <typename R>
-__device__ __forceinline__ void set_times(Lane<R> &p, const KArgs &a, const JobDev &J)
+template <typename R, int FORM, int G>
+__device__ __forceinline__ void set_times(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J)
 {
-    const double *times = a.times + J.times_off;
+    const double *times = times_of<FORM, G>(a, sh) + J.times_off;
     p.tnext = (p.tcur < p.n_times) ? times[p.tcur] : __builtin_huge_val();
     p.tend = (p.n_times > 0) ? times[p.n_times - 1] : __builtin_huge_val();
 }
 
-template <typename R, int G>
+template <typename R, int FORM, int G>
 __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, uint64_t qidx, int job)
 {
     const uint64_t pid = J.pid0 + (qidx - J.base - (uint64_t)a.n_resume);
@@ -474,7 +491,7 @@ __device__ void emit(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev 
     p.Lz = 0.0;
     p.h = 0.0;
     p.tcur = 0;
-    set_times(p, a, J);
+    set_times<R, FORM, G>(p, a, sh, J);
 
     const uint32_t plo = (uint32_t)pid, phi = (uint32_t)(pid >> 32);
     // the emission blocks, with the lane's key schedule where the kernel keeps one
@@ -804,12 +821,13 @@ __device__ __forceinline__ void snapshot_commit(Lane<R> &p, const KArgs &a, cons
 // (production half-space kernel) a crossing is recorded in registers and scored
 // later together with other lanes' (snapshot_commit), so that the divergent
 // cell and atomic work runs once for many lanes.
-template <typename R, bool DEFER>
-__device__ void score_snapshots(Lane<R> &p, const KArgs &a, const JobDev &J, double seg)
+template <typename R, int FORM, int G>
+__device__ void score_snapshots(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, double seg)
 {
+    constexpr bool DEFER = defer_snapshots<R, FORM, G>();
     const double ta = p.t, tb = p.t + seg;
     // the production kernel keeps the job's offset in the lane (one load fewer in turn)
-    const double *times = a.times + (DEFER ? p.toff : J.times_off);
+    const double *times = times_of<FORM, G>(a, sh) + (DEFER ? p.toff : J.times_off);
     while (p.tnext < tb) {
         const double tj = p.tnext;
         if (tj >= ta) {
@@ -921,7 +939,7 @@ __device__ __forceinline__ void region_flush(Lane<R> &p, const KArgs &a, const S
 // region adds s (hi - lo) and s v Omega_z (hi - lo) to the particle's sums of the
 // window(s) it falls in.  Same operations, in the same order, as the FP64
 // reference, so the parity mode agrees.
-template <typename R>
+template <typename R, int FORM, int G>
 __device__ void score_region(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J, R seg)
 {
     // the region's bounds, read together (one wait for all of them)
@@ -970,7 +988,7 @@ __device__ void score_region(Lane<R> &p, const KArgs &a, const Shared &sh, const
         p.rq += (double)p.s * (double)p.v * (double)p.oz * (t1 - t0);
         return;
     }
-    const double *times = a.times + J.times_off;
+    const double *times = times_of<FORM, G>(a, sh) + J.times_off;
     int j = (p.rwin > 0) ? p.rwin : 0;
     double w0 = (j == 0) ? 0.0 : times[j - 1];
     for (; j < p.n_times; ++j) {
@@ -1177,7 +1195,7 @@ __device__ void resume(Lane<R> &p, const KArgs &a, const Shared &sh, uint32_t i)
     p.nbound = S.nbound;
     p.last = S.last;
     p.tcur = S.tcur;
-    set_times(p, a, J);
+    set_times<R, FORM_EPOCH, G>(p, a, sh, J);
     p.s = (R)S.sign;
     p.rt = S.rt;
     p.rq = S.rq;
@@ -1331,10 +1349,10 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
         }
         if (G == GEOM_ANY || G == GEOM_HALF) {
             const double tb_abs = p.t + (double)seg;
-            if (p.tnext < tb_abs) score_snapshots<R, defer_snapshots<R, FORM, G>()>(p, a, J, (double)seg);
+            if (p.tnext < tb_abs) score_snapshots<R, FORM, G>(p, a, sh, J, (double)seg);
             // windowed region tally (a launch-wide flag skips the test when no job
             // has one); most segments lie wholly above the region
-            if (a.any_region && fmin(p.z, p.z + p.v * p.oz * seg) < p.rzhi) score_region(p, a, sh, J, seg);
+            if (a.any_region && fmin(p.z, p.z + p.v * p.oz * seg) < p.rzhi) score_region<R, FORM, G>(p, a, sh, J, seg);
             if (tb_abs > p.tend) return 1;  // step VI
         }
         // move
@@ -1437,6 +1455,9 @@ __device__ Shared setup_shared(const KArgs &a, unsigned char *smem)
     sh.lstats = reinterpret_cast<unsigned long long *>(smem + off);
     if (a.lds_stats)
         for (int i = threadIdx.x; i < a.n_jobs * kStats; i += blockDim.x) sh.lstats[i] = 0ull;
+    // the sample times after the counters (persistent half-space launches)
+    sh.ltimes = reinterpret_cast<double *>(smem + off + (a.lds_stats ? (size_t)a.n_jobs * kStats * 8 : 0));
+    for (int i = threadIdx.x; i < a.times_lds; i += blockDim.x) sh.ltimes[i] = a.times[i];
     __syncthreads();
     return sh;
 }
@@ -1506,7 +1527,7 @@ __global__ void __launch_bounds__(256) plain_kernel(KArgs a)
         const int job = find_job(a, q, 0);
         const JobDev &J = a.jobs[job];
         Lane<R> p;
-        emit<R, G>(p, a, sh, J, q, job);
+        emit<R, FORM_PLAIN, G>(p, a, sh, J, q, job);
         int r;
         do {
             r = step<R, FORM_PLAIN, G>(p, a, sh, J, wave_key_active(p), 1u);
@@ -1594,7 +1615,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                     } else {
                         const uint64_t qn = BOUNDED ? q - (uint64_t)a.n_resume : q;
                         job = find_job(a, qn, job);
-                        emit<R, G>(p, a, sh, a.jobs[job], q, job);
+                        emit<R, PF, G>(p, a, sh, a.jobs[job], q, job);
                     }
                     alive = true;
                 }
@@ -1630,7 +1651,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                             resume<R, G>(p, a, sh, (uint32_t)q);
                         } else {
                             job = find_job(a, q - (uint64_t)a.n_resume, job);
-                            emit<R, G>(p, a, sh, a.jobs[job], q, job);
+                            emit<R, PF, G>(p, a, sh, a.jobs[job], q, job);
                         }
                         suspend<R, PF, G>(p, a, sh);
                     }
