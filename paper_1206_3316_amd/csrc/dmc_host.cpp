@@ -454,8 +454,14 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
     int32_t n_times_all = 0;
     for (int i = 0; i < n_jobs; ++i) n_times_all = std::max(n_times_all, devs[i].times_off + devs[i].n_times);
     const bool bounded_launch = b.drain_iters > 0 || b.n_resume > 0;
-    const bool times_lds = spec == GEOM_HALF && o.form == DMC_FORM_PERSISTENT && !bounded_launch;
-    if (times_lds && n_times_all > kLdsTimes) spec = GEOM_ANY;
+    const bool unbounded_persistent = o.form == DMC_FORM_PERSISTENT && !bounded_launch;
+    if (unbounded_persistent && spec == GEOM_HALF && n_times_all > kLdsTimes) spec = GEOM_ANY;
+    // the persistent specialised kernels (not time-bounded) read the job table from
+    // LDS: it must fit, else the generic kernel runs
+    if (unbounded_persistent && spec != GEOM_ANY && (size_t)n_jobs * sizeof(JobDev) > (size_t)kLdsJobsBytes)
+        spec = GEOM_ANY;
+    const bool times_lds = unbounded_persistent && spec == GEOM_HALF;
+    const bool jobs_lds = unbounded_persistent && spec != GEOM_ANY;
     KArgs a{};
     {
         const double g = M->scatter_g;
@@ -505,8 +511,10 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
         return fail(DMC_E_INVALID, "time-bounded launches need the persistent form");
     if (b.n_resume && !b.drain_iters) return fail(DMC_E_INVALID, "resuming needs a time-bounded launch");
     const size_t stats_lds = a.lds_stats ? (size_t)n_jobs * kStats * 8 : 0;
-    a.times_lds = (spec == GEOM_HALF && times_lds) ? n_times_all : 0;
-    const size_t times_bytes = (size_t)a.times_lds * 8;
+    a.times_lds = times_lds ? n_times_all : 0;
+    a.jobs_lds = jobs_lds ? 1 : 0;
+    // sample times after the counters, then the job table at a 16-byte boundary
+    const size_t tail_bytes = (size_t)a.times_lds * 8 + (jobs_lds ? 16 + (size_t)n_jobs * sizeof(JobDev) : 0);
     for (int i = 0; i < n_jobs; ++i) {
         JobDev &d = devs[i];
         d.lds_bins = d.lds_kappa = d.lds_hj = d.lds_dispx = d.lds_region = d.lds_field = -1;
@@ -518,9 +526,9 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
         // LDS: gain table + per-state data, then privatised tallies while they fit
         const size_t tab = (((size_t)a.kpad * 4 + 15) & ~size_t(15)) + (size_t)M->K * 16;
         const size_t cap = (size_t)max_lds_bytes();
-        if (tab + stats_lds + times_bytes + 1024 > cap)
+        if (tab + stats_lds + tail_bytes + 1024 > cap)
             return fail(DMC_E_UNSUPPORTED, "persistent form: material tables do not fit in LDS");
-        const size_t budget = (cap - tab - stats_lds - times_bytes - 16) / 8;  // doubles
+        const size_t budget = (cap - tab - stats_lds - tail_bytes - 16) / 8;  // doubles
         int32_t lo = 0;
         if (o.lds_tally) {
             for (int i = 0; i < n_jobs; ++i) {
@@ -564,7 +572,7 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
         a.bins_lds_all = 1;
         for (int i = 0; i < n_jobs; ++i)
             if (devs[i].off_bins >= 0 && devs[i].lds_bins < 0) a.bins_lds_all = 0;
-        lds_bytes = ((tab + 15) & ~size_t(15)) + (size_t)lo * 8 + stats_lds + times_bytes;
+        lds_bytes = ((tab + 15) & ~size_t(15)) + (size_t)lo * 8 + stats_lds + tail_bytes;
         a.chunk = o.chunk > 0 ? o.chunk : 1024;
         a.refill_min = o.refill_min > 0 ? o.refill_min : 16;
         block = o.block > 0 ? o.block : (lds_bytes > 64 * 1024 ? 1024 : 512);

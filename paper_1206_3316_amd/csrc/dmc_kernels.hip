@@ -273,7 +273,23 @@ struct Shared {
     double *ltally;              // LDS tallies (slots used only where a job's lds offset >= 0)
     unsigned long long *lstats;  // LDS per-job counters (used only if KArgs::lds_stats)
     double *ltimes;              // LDS copy of the launch's sample times (persistent half-space kernel)
+    JobDev *ljobs;               // LDS copy of the job table (persistent specialised kernels)
 };
+
+// The persistent specialised kernels read the job table from its LDS copy (the
+// host sizes LDS for it, or runs the generic kernel); the others from KArgs::jobs.
+template <int FORM, int G>
+__device__ constexpr bool jobs_in_lds()
+{
+    return FORM == FORM_PERSISTENT && (G == GEOM_SLAB || G == GEOM_HALF || G == GEOM_GRAD);
+}
+
+template <int FORM, int G>
+__device__ __forceinline__ const JobDev *jobs_of(const KArgs &a, const Shared &sh)
+{
+    if constexpr (jobs_in_lds<FORM, G>()) return sh.ljobs;
+    return a.jobs;
+}
 
 // The persistent half-space kernel reads the sample times from their LDS copy
 // (the host sizes LDS for them, or runs the generic kernel); the others read
@@ -1409,10 +1425,10 @@ __device__ __forceinline__ int step(Lane<R> &p, const KArgs &a, const Shared &sh
     }
 }
 
-__device__ __forceinline__ int find_job(const KArgs &a, uint64_t q, int hint)
+__device__ __forceinline__ int find_job(const JobDev *jt, int n_jobs, uint64_t q, int hint)
 {
     int j = hint;
-    while (j + 1 < a.n_jobs && q >= a.jobs[j + 1].base) ++j;
+    while (j + 1 < n_jobs && q >= jt[j + 1].base) ++j;
     return j;
 }
 
@@ -1455,9 +1471,19 @@ __device__ Shared setup_shared(const KArgs &a, unsigned char *smem)
     sh.lstats = reinterpret_cast<unsigned long long *>(smem + off);
     if (a.lds_stats)
         for (int i = threadIdx.x; i < a.n_jobs * kStats; i += blockDim.x) sh.lstats[i] = 0ull;
-    // the sample times after the counters (persistent half-space launches)
-    sh.ltimes = reinterpret_cast<double *>(smem + off + (a.lds_stats ? (size_t)a.n_jobs * kStats * 8 : 0));
+    // the sample times after the counters (persistent half-space launches), then
+    // the job table at a 16-byte boundary (persistent specialised launches)
+    const size_t toff = off + (a.lds_stats ? (size_t)a.n_jobs * kStats * 8 : 0);
+    sh.ltimes = reinterpret_cast<double *>(smem + toff);
     for (int i = threadIdx.x; i < a.times_lds; i += blockDim.x) sh.ltimes[i] = a.times[i];
+    const size_t joff = (toff + (size_t)a.times_lds * 8 + 15) & ~(size_t)15;
+    sh.ljobs = reinterpret_cast<JobDev *>(smem + joff);
+    if (a.jobs_lds) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.jobs);
+        uint4 *dst = reinterpret_cast<uint4 *>(sh.ljobs);
+        const int words = a.n_jobs * (int)(sizeof(JobDev) / 16);
+        for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+    }
     __syncthreads();
     return sh;
 }
@@ -1524,7 +1550,7 @@ __global__ void __launch_bounds__(256) plain_kernel(KArgs a)
     const Shared sh = setup_shared<R, FORM_PLAIN>(a, smem);
     const uint64_t q = a.qbegin + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q < a.total) {
-        const int job = find_job(a, q, 0);
+        const int job = find_job(a.jobs, a.n_jobs, q, 0);
         const JobDev &J = a.jobs[job];
         Lane<R> p;
         emit<R, FORM_PLAIN, G>(p, a, sh, J, q, job);
@@ -1554,6 +1580,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
     extern __shared__ __align__(16) unsigned char smem[];
     const Shared sh = setup_shared<R, FORM_PERSISTENT>(a, smem);
     constexpr int PF = BOUNDED ? FORM_EPOCH : FORM_PERSISTENT;
+    const JobDev *const jt = jobs_of<PF, G>(a, sh);
     const int lane = (int)(threadIdx.x & 63);
     Lane<R> p;
     bool alive = false;
@@ -1585,7 +1612,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
         if (HOLD && n_free == 64) hold = false;
         if (n_free > 0 && have_work && !(HOLD && hold) && (n_free >= a.refill_min || n_free == 64)) {
             if (ended) {
-                finish<R, PF, G>(p, a, sh, a.jobs[p.job], ended == 2);
+                finish<R, PF, G>(p, a, sh, jt[p.job], ended == 2);
                 ended = 0;
             }
             while (need) {
@@ -1614,8 +1641,8 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                         resume<R, G>(p, a, sh, (uint32_t)q);
                     } else {
                         const uint64_t qn = BOUNDED ? q - (uint64_t)a.n_resume : q;
-                        job = find_job(a, qn, job);
-                        emit<R, PF, G>(p, a, sh, a.jobs[job], q, job);
+                        job = find_job(jt, a.n_jobs, qn, job);
+                        emit<R, PF, G>(p, a, sh, jt[job], q, job);
                     }
                     alive = true;
                 }
@@ -1637,7 +1664,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
             // started, to the next launch
             if (++drain > a.drain_iters) {
                 if (ended) {
-                    finish<R, PF, G>(p, a, sh, a.jobs[p.job], ended == 2);
+                    finish<R, PF, G>(p, a, sh, jt[p.job], ended == 2);
                     ended = 0;
                 }
                 if (alive) suspend<R, PF, G>(p, a, sh);
@@ -1650,8 +1677,8 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
                         if (q < (uint64_t)a.n_resume) {
                             resume<R, G>(p, a, sh, (uint32_t)q);
                         } else {
-                            job = find_job(a, q - (uint64_t)a.n_resume, job);
-                            emit<R, PF, G>(p, a, sh, a.jobs[job], q, job);
+                            job = find_job(jt, a.n_jobs, q - (uint64_t)a.n_resume, job);
+                            emit<R, PF, G>(p, a, sh, jt[job], q, job);
                         }
                         suspend<R, PF, G>(p, a, sh);
                     }
@@ -1698,7 +1725,7 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
         // long-running particle, the budget graded by its age
         const uint32_t hops = (G == GEOM_GRAD && __popcll(wave_lanes & ~need) <= 4) ? 64u : old_hops;
         if (alive) {
-            const JobDev &J = a.jobs[p.job];
+            const JobDev &J = jt[p.job];
             const int r = step<R, PF, G>(p, a, sh, J, wk, hops);
             if (r != 0) {
                 if (DEFER_FINISH)
@@ -1716,14 +1743,14 @@ __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
             if (__popcll(cm) >= 16) {
                 const int jw = __builtin_amdgcn_readlane(p.job, __ffsll((unsigned long long)cm) - 1);
                 if (__ballot(mine && p.job != jw) == 0ull) {
-                    if (mine) snapshot_commit(p, a, a.jobs[jw]);
+                    if (mine) snapshot_commit(p, a, jt[jw]);
                 } else if (mine) {
-                    snapshot_commit(p, a, a.jobs[p.job]);
+                    snapshot_commit(p, a, jt[p.job]);
                 }
             }
         }
     }
-    if (ended) finish<R, PF, G>(p, a, sh, a.jobs[p.job], ended == 2);
+    if (ended) finish<R, PF, G>(p, a, sh, jt[p.job], ended == 2);
     flush_shared(a, sh);
 }
 
