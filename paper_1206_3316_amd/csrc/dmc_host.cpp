@@ -456,12 +456,12 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
     const bool bounded_launch = b.drain_iters > 0 || b.n_resume > 0;
     const bool unbounded_persistent = o.form == DMC_FORM_PERSISTENT && !bounded_launch;
     if (unbounded_persistent && spec == GEOM_HALF && n_times_all > kLdsTimes) spec = GEOM_ANY;
-    // the persistent specialised kernels (not time-bounded) read the job table from
-    // LDS: it must fit, else the generic kernel runs
-    if (unbounded_persistent && spec != GEOM_ANY && (size_t)n_jobs * sizeof(JobDev) > (size_t)kLdsJobsBytes)
-        spec = GEOM_ANY;
+    // persistent launches read the job table from LDS when it fits; the specialised
+    // kernels exist only in that form, so a larger table takes the generic kernel
+    const bool jobs_lds =
+        o.form == DMC_FORM_PERSISTENT && (size_t)n_jobs * sizeof(JobDev) <= (size_t)kLdsJobsBytes;
+    if (o.form == DMC_FORM_PERSISTENT && !jobs_lds) spec = GEOM_ANY;
     const bool times_lds = unbounded_persistent && spec == GEOM_HALF;
-    const bool jobs_lds = unbounded_persistent && spec != GEOM_ANY;
     KArgs a{};
     {
         const double g = M->scatter_g;
@@ -576,7 +576,7 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
         a.chunk = o.chunk > 0 ? o.chunk : 1024;
         a.refill_min = o.refill_min > 0 ? o.refill_min : 16;
         block = o.block > 0 ? o.block : (lds_bytes > 64 * 1024 ? 1024 : 512);
-        const int per_cu = occupancy_blocks(o.precision, o.form, spec, bounded_launch, block, lds_bytes);
+        const int per_cu = occupancy_blocks(o.precision, o.form, spec, bounded_launch, jobs_lds, block, lds_bytes);
         grid = o.grid_blocks > 0 ? o.grid_blocks : device_cus() * per_cu;
         if (b.drain_iters) {
             // every lane may suspend one particle and every wave the unstarted rest of

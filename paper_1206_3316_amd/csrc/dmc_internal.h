@@ -13,7 +13,7 @@ constexpr int kMaxJobs = 4096;
 constexpr int kMaxBins = 4096;
 constexpr int kMaxTimes = 1024;
 constexpr int kMaxHj = 1024;
-constexpr int kLdsJobsBytes = 48 * 1024;  // job table staged in LDS by the persistent specialised kernels, at most
+constexpr int kLdsJobsBytes = 48 * 1024;  // job table staged in LDS by the persistent kernels, at most
 constexpr int kLdsTimes = 2048;           // sample times staged in LDS by the persistent half-space kernel, at most
 constexpr int kLdsStatJobs = 64;         // per-job counters privatised in LDS up to this many jobs
 constexpr int kStats = 7;                // particles, scatters, boundary, iterations, capped, suspended,
@@ -95,7 +95,7 @@ struct KArgs {
     int32_t gain_bits, flux_bits, init_bits;
     int32_t any_region;             // 1: some job of the launch has a windowed region tally
     int32_t times_lds;              // doubles of times staged in LDS (persistent half-space launches), else 0
-    int32_t jobs_lds;               // 1: the job table is staged in LDS (persistent specialised launches)
+    int32_t jobs_lds;               // 1: the job table is staged in LDS (persistent launches whose table fits)
     const uint32_t *gain_packed, *flux_packed, *init_packed;
     const float4 *st32;             // per state: v, tau, 1/tau, 0
     const double2 *st64;            // per state: v, tau
@@ -168,7 +168,7 @@ enum OpCost : int32_t {
 };
 hipError_t launch_op_cost(int op, uint32_t iters, int blocks, uint32_t *out, hipStream_t stream);
 int max_lds_bytes();
-int occupancy_blocks(int precision, int form, int spec, bool bounded, int block, size_t lds_bytes);
+int occupancy_blocks(int precision, int form, int spec, bool bounded, bool jl, int block, size_t lds_bytes);
 // The specialised kernel a set of jobs can use.
 int kernel_spec(const JobDev *jobs, int n_jobs);
 

@@ -273,23 +273,8 @@ struct Shared {
     double *ltally;              // LDS tallies (slots used only where a job's lds offset >= 0)
     unsigned long long *lstats;  // LDS per-job counters (used only if KArgs::lds_stats)
     double *ltimes;              // LDS copy of the launch's sample times (persistent half-space kernel)
-    JobDev *ljobs;               // LDS copy of the job table (persistent specialised kernels)
+    JobDev *ljobs;               // LDS copy of the job table (persistent launches whose table fits)
 };
-
-// The persistent specialised kernels read the job table from its LDS copy (the
-// host sizes LDS for it, or runs the generic kernel); the others from KArgs::jobs.
-template <int FORM, int G>
-__device__ constexpr bool jobs_in_lds()
-{
-    return FORM == FORM_PERSISTENT && (G == GEOM_SLAB || G == GEOM_HALF || G == GEOM_GRAD);
-}
-
-template <int FORM, int G>
-__device__ __forceinline__ const JobDev *jobs_of(const KArgs &a, const Shared &sh)
-{
-    if constexpr (jobs_in_lds<FORM, G>()) return sh.ljobs;
-    return a.jobs;
-}
 
 // The persistent half-space kernel reads the sample times from their LDS copy
 // (the host sizes LDS for them, or runs the generic kernel); the others read
@@ -1574,13 +1559,15 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int src)
 
 // BOUNDED: time-bounded launch (serving epochs): resumes suspended particles
 // and suspends the live ones a fixed number of flights after the queue runs dry.
-template <typename R, int G, bool BOUNDED>
+// JL: the job table is read from its LDS copy (the host stages it whenever it
+// fits, and runs the specialised kernels only then).
+template <typename R, int G, bool BOUNDED, bool JL>
 __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const Shared sh = setup_shared<R, FORM_PERSISTENT>(a, smem);
     constexpr int PF = BOUNDED ? FORM_EPOCH : FORM_PERSISTENT;
-    const JobDev *const jt = jobs_of<PF, G>(a, sh);
+    const JobDev *const jt = JL ? sh.ljobs : a.jobs;
     const int lane = (int)(threadIdx.x & 63);
     Lane<R> p;
     bool alive = false;
@@ -1890,25 +1877,34 @@ hipError_t launch_debug_math(const double *x, double *lg, double *sn, double *cs
 
 namespace {
 
+// The specialised kernels exist only with the job table in LDS (the host runs the
+// generic kernel when it does not fit); the generic kernel in both forms.
 template <typename R, int G>
-const void *kernel_ptr(int form, bool bounded)
+const void *kernel_ptr(int form, bool bounded, bool jl)
 {
     if (form == FORM_PLAIN) return (const void *)plain_kernel<R, G>;
-    return bounded ? (const void *)persistent_kernel<R, G, true> : (const void *)persistent_kernel<R, G, false>;
+    if constexpr (G == GEOM_ANY) {
+        if (!jl)
+            return bounded ? (const void *)persistent_kernel<R, G, true, false>
+                           : (const void *)persistent_kernel<R, G, false, false>;
+    } else {
+        if (!jl) return nullptr;
+    }
+    return bounded ? (const void *)persistent_kernel<R, G, true, true> : (const void *)persistent_kernel<R, G, false, true>;
 }
 
 template <typename R>
-const void *pick_geom(int spec, int form, bool bounded)
+const void *pick_geom(int spec, int form, bool bounded, bool jl)
 {
-    if (spec == GEOM_SLAB) return kernel_ptr<R, GEOM_SLAB>(form, bounded);
-    if (spec == GEOM_HALF) return kernel_ptr<R, GEOM_HALF>(form, bounded);
-    if (spec == GEOM_GRAD) return kernel_ptr<R, GEOM_GRAD>(form, bounded);
-    return kernel_ptr<R, GEOM_ANY>(form, bounded);
+    if (spec == GEOM_SLAB) return kernel_ptr<R, GEOM_SLAB>(form, bounded, jl);
+    if (spec == GEOM_HALF) return kernel_ptr<R, GEOM_HALF>(form, bounded, jl);
+    if (spec == GEOM_GRAD) return kernel_ptr<R, GEOM_GRAD>(form, bounded, jl);
+    return kernel_ptr<R, GEOM_ANY>(form, bounded, jl);
 }
 
-const void *pick_kernel(int precision, int form, int spec, bool bounded)
+const void *pick_kernel(int precision, int form, int spec, bool bounded, bool jl)
 {
-    return precision == 0 ? pick_geom<double>(spec, form, bounded) : pick_geom<float>(spec, form, bounded);
+    return precision == 0 ? pick_geom<double>(spec, form, bounded, jl) : pick_geom<float>(spec, form, bounded, jl);
 }
 
 }  // namespace
@@ -1916,7 +1912,8 @@ const void *pick_kernel(int precision, int form, int spec, bool bounded)
 hipError_t launch_trajectories(const KArgs &a, int precision, int form, int spec, int block, int grid,
                                size_t lds_bytes, hipStream_t stream)
 {
-    const void *f = pick_kernel(precision, form, spec, a.drain_iters > 0 || a.n_resume > 0);
+    const void *f = pick_kernel(precision, form, spec, a.drain_iters > 0 || a.n_resume > 0, a.jobs_lds != 0);
+    if (!f) return hipErrorInvalidValue;
     if (lds_bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) return e;
@@ -1956,9 +1953,10 @@ hipError_t launch_debug_alias(const uint32_t *packed, int bits, const uint32_t *
 
 int max_lds_bytes() { return 160 * 1024; }
 
-int occupancy_blocks(int precision, int form, int spec, bool bounded, int block, size_t lds_bytes)
+int occupancy_blocks(int precision, int form, int spec, bool bounded, bool jl, int block, size_t lds_bytes)
 {
-    const void *f = pick_kernel(precision, form, spec, bounded);
+    const void *f = pick_kernel(precision, form, spec, bounded, jl);
+    if (!f) return 1;
     if (lds_bytes > 64 * 1024) {
         if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) != hipSuccess) {
             (void)hipGetLastError();
