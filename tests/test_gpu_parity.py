@@ -273,6 +273,36 @@ def test_batch_equals_solo_and_parameter_invariance():
             assert rel_diff(other.raw(j), ref.raw(j)) <= 1e-12, (params, j)
 
 
+def test_launches_beyond_the_lds_tables_equal_solo_runs():
+    """A launch whose job table exceeds its LDS copy (over 113 jobs) runs the
+    generic kernel with the table in global memory, and a half-space launch whose
+    sample times exceed theirs (over 2048) the generic kernel too: each job's
+    tallies equal its solo run, which takes a specialised kernel with both tables
+    in LDS."""
+    from gpu_cases import small_spot
+    si = di.silicon_like()
+    mat = b.Material(si)
+    jobs = []
+    for i in range(120):
+        if i % 3 == 0:
+            jobs.append(di.slab_job(si, 40e-9 + 5e-9 * (i % 7), 300, seed=5000 + i, n_bins=8))
+        elif i % 3 == 1:
+            jobs.append(di.pore_cell(60e-9, 0.2, 300, seed=5000 + i, material=si, kmax=40, n_hj=10))
+        else:
+            jobs.append(small_spot(n=200, seed=5000 + i, grid=4, n_times=4))
+    print("case 120-job batch", flush=True)
+    batch = b.simulate(jobs, material=mat)
+    for j in (0, 1, 2, 58, 119):
+        solo = b.simulate([jobs[j]], material=mat)
+        assert rel_diff(batch.raw(j), solo.raw(0)) <= 1e-12, j
+    print("case 3 half-space jobs x 1000 sample times", flush=True)
+    spots = [small_spot(n=400, seed=6000 + i, grid=4, n_times=1000, t_max=1e-10) for i in range(3)]
+    batch = b.simulate(spots, material=mat)
+    for j in range(3):
+        solo = b.simulate([spots[j]], material=mat)
+        assert rel_diff(batch.raw(j), solo.raw(0)) <= 1e-12, j
+
+
 def test_autotuner_choice_is_valid_cached_and_result_invariant():
     """The tuner returns parameters from its search space, answers a repeated
     signature from its cache, and the tuned launch gives the default launch's
