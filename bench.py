@@ -140,7 +140,7 @@ def op_costs(b):
 # WRITE_SIZE runs (profiles/), scaled by the same counters' reading for a plain
 # device copy of known size (bench.py --copy-probe); valid only for the kernel
 # source it was measured on.
-TRAFFIC = {"kernel_sha1": "3dd3ad61523a8b7edc8c8528c71c2d6e389964fa", "bytes": 54582333}  # profiles/persistent_kernel_slab_12films_counters.md
+TRAFFIC = {"kernel_sha1": "4d80a0076ffeceff45462c75a59d1795746b6454", "bytes": 54574141}  # profiles/persistent_kernel_slab_12films_counters.md
 CU, LANES_PER_CU_CLK, CLOCK = 256, 64, 2.4e9
 PEAK_LANE_OPS = CU * LANES_PER_CU_CLK * CLOCK  # 3.93e13 full-rate VALU lane-ops/s
 
