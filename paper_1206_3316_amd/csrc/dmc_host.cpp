@@ -454,14 +454,13 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
     int32_t n_times_all = 0;
     for (int i = 0; i < n_jobs; ++i) n_times_all = std::max(n_times_all, devs[i].times_off + devs[i].n_times);
     const bool bounded_launch = b.drain_iters > 0 || b.n_resume > 0;
-    const bool unbounded_persistent = o.form == DMC_FORM_PERSISTENT && !bounded_launch;
-    if (unbounded_persistent && spec == GEOM_HALF && n_times_all > kLdsTimes) spec = GEOM_ANY;
-    // persistent launches read the job table from LDS when it fits; the specialised
-    // kernels exist only in that form, so a larger table takes the generic kernel
-    const bool jobs_lds =
-        o.form == DMC_FORM_PERSISTENT && (size_t)n_jobs * sizeof(JobDev) <= (size_t)kLdsJobsBytes;
+    // persistent launches read the job table and the sample times from LDS when both
+    // fit; the specialised kernels exist only in that form, so larger tables take
+    // the generic kernel
+    const bool jobs_lds = o.form == DMC_FORM_PERSISTENT &&
+                          (size_t)n_jobs * sizeof(JobDev) <= (size_t)kLdsJobsBytes && n_times_all <= kLdsTimes;
     if (o.form == DMC_FORM_PERSISTENT && !jobs_lds) spec = GEOM_ANY;
-    const bool times_lds = unbounded_persistent && spec == GEOM_HALF;
+    const bool times_lds = jobs_lds;
     KArgs a{};
     {
         const double g = M->scatter_g;

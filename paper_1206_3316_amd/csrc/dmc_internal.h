@@ -14,7 +14,7 @@ constexpr int kMaxBins = 4096;
 constexpr int kMaxTimes = 1024;
 constexpr int kMaxHj = 1024;
 constexpr int kLdsJobsBytes = 48 * 1024;  // job table staged in LDS by the persistent kernels, at most
-constexpr int kLdsTimes = 2048;           // sample times staged in LDS by the persistent half-space kernel, at most
+constexpr int kLdsTimes = 2048;           // sample times staged with it, at most
 constexpr int kLdsStatJobs = 64;         // per-job counters privatised in LDS up to this many jobs
 constexpr int kStats = 7;                // particles, scatters, boundary, iterations, capped, suspended,
                                          // flights (Philox STEP blocks drawn)
@@ -94,8 +94,8 @@ struct KArgs {
     unsigned long long *queue;      // next queue index (persistent form)
     int32_t gain_bits, flux_bits, init_bits;
     int32_t any_region;             // 1: some job of the launch has a windowed region tally
-    int32_t times_lds;              // doubles of times staged in LDS (persistent half-space launches), else 0
-    int32_t jobs_lds;               // 1: the job table is staged in LDS (persistent launches whose table fits)
+    int32_t times_lds;              // doubles of times staged in LDS (with the job table), else 0
+    int32_t jobs_lds;               // 1: the job table and the times are staged in LDS (persistent launches where both fit)
     const uint32_t *gain_packed, *flux_packed, *init_packed;
     const float4 *st32;             // per state: v, tau, 1/tau, 0
     const double2 *st64;            // per state: v, tau

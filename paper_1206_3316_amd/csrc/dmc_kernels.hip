@@ -272,25 +272,10 @@ struct Shared {
     const void *st;              // per-state data: LDS (persistent) or global (plain)
     double *ltally;              // LDS tallies (slots used only where a job's lds offset >= 0)
     unsigned long long *lstats;  // LDS per-job counters (used only if KArgs::lds_stats)
-    double *ltimes;              // LDS copy of the launch's sample times (persistent half-space kernel)
-    JobDev *ljobs;               // LDS copy of the job table (persistent launches whose table fits)
+    double *ltimes;              // LDS copy of the launch's sample times (persistent launches whose tables fit)
+    JobDev *ljobs;               // LDS copy of the job table (the same launches)
+    const double *times;         // the sample times read: the LDS copy in those launches, else KArgs::times
 };
-
-// The persistent half-space kernel reads the sample times from their LDS copy
-// (the host sizes LDS for them, or runs the generic kernel); the others read
-// KArgs::times.
-template <int FORM, int G>
-__device__ constexpr bool times_in_lds()
-{
-    return FORM == FORM_PERSISTENT && G == GEOM_HALF;
-}
-
-template <int FORM, int G>
-__device__ __forceinline__ const double *times_of(const KArgs &a, const Shared &sh)
-{
-    if constexpr (times_in_lds<FORM, G>()) return sh.ltimes;
-    return a.times;
-}
 
 template <typename R>
 __device__ __forceinline__ void load_state(Lane<R> &p, const KArgs &a, const Shared &sh, uint32_t m);
@@ -471,7 +456,7 @@ __device__ __forceinline__ void bind_job(Lane<R> &p, const JobDev &J, uint64_t p
 template <typename R, int FORM, int G>
 __device__ __forceinline__ void set_times(Lane<R> &p, const KArgs &a, const Shared &sh, const JobDev &J)
 {
-    const double *times = times_of<FORM, G>(a, sh) + J.times_off;
+    const double *times = sh.times + J.times_off;
     p.tnext = (p.tcur < p.n_times) ? times[p.tcur] : __builtin_huge_val();
     p.tend = (p.n_times > 0) ? times[p.n_times - 1] : __builtin_huge_val();
 }
@@ -828,7 +813,7 @@ __device__ void score_snapshots(Lane<R> &p, const KArgs &a, const Shared &sh, co
     constexpr bool DEFER = defer_snapshots<R, FORM, G>();
     const double ta = p.t, tb = p.t + seg;
     // the production kernel keeps the job's offset in the lane (one load fewer in turn)
-    const double *times = times_of<FORM, G>(a, sh) + (DEFER ? p.toff : J.times_off);
+    const double *times = sh.times + (DEFER ? p.toff : J.times_off);
     while (p.tnext < tb) {
         const double tj = p.tnext;
         if (tj >= ta) {
@@ -989,7 +974,7 @@ __device__ void score_region(Lane<R> &p, const KArgs &a, const Shared &sh, const
         p.rq += (double)p.s * (double)p.v * (double)p.oz * (t1 - t0);
         return;
     }
-    const double *times = times_of<FORM, G>(a, sh) + J.times_off;
+    const double *times = sh.times + J.times_off;
     int j = (p.rwin > 0) ? p.rwin : 0;
     double w0 = (j == 0) ? 0.0 : times[j - 1];
     for (; j < p.n_times; ++j) {
@@ -1202,8 +1187,8 @@ __device__ void resume(Lane<R> &p, const KArgs &a, const Shared &sh, uint32_t i)
     p.rq = S.rq;
     p.rwin = S.rwin;
     if (p.rwin >= 0) {
-        p.rwbeg = (p.rwin == 0) ? 0.0 : a.times[J.times_off + p.rwin - 1];
-        p.rwend = a.times[J.times_off + p.rwin];
+        p.rwbeg = (p.rwin == 0) ? 0.0 : sh.times[J.times_off + p.rwin - 1];
+        p.rwend = sh.times[J.times_off + p.rwin];
     }
     load_state(p, a, sh, S.m);
     set_kbin(p);
@@ -1424,7 +1409,9 @@ __device__ __forceinline__ int find_job(const JobDev *jt, int n_jobs, uint64_t q
 // counters.  The plain form keeps the tables in global memory and only the
 // counters in LDS.  Pointers into LDS are always derived from the shared
 // array so the compiler emits LDS instructions for them.
-template <typename R, int FORM>
+// JL: the launch's job table and sample times are staged in LDS (the host sizes
+// LDS for them whenever both fit) and read from there.
+template <typename R, int FORM, bool JL>
 __device__ Shared setup_shared(const KArgs &a, unsigned char *smem)
 {
     Shared sh;
@@ -1456,13 +1443,13 @@ __device__ Shared setup_shared(const KArgs &a, unsigned char *smem)
     sh.lstats = reinterpret_cast<unsigned long long *>(smem + off);
     if (a.lds_stats)
         for (int i = threadIdx.x; i < a.n_jobs * kStats; i += blockDim.x) sh.lstats[i] = 0ull;
-    // the sample times after the counters (persistent half-space launches), then
-    // the job table at a 16-byte boundary (persistent specialised launches)
+    // the sample times after the counters, then the job table at a 16-byte boundary
     const size_t toff = off + (a.lds_stats ? (size_t)a.n_jobs * kStats * 8 : 0);
     sh.ltimes = reinterpret_cast<double *>(smem + toff);
     for (int i = threadIdx.x; i < a.times_lds; i += blockDim.x) sh.ltimes[i] = a.times[i];
     const size_t joff = (toff + (size_t)a.times_lds * 8 + 15) & ~(size_t)15;
     sh.ljobs = reinterpret_cast<JobDev *>(smem + joff);
+    sh.times = JL ? sh.ltimes : a.times;
     if (a.jobs_lds) {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.jobs);
         uint4 *dst = reinterpret_cast<uint4 *>(sh.ljobs);
@@ -1532,7 +1519,7 @@ template <typename R, int G>
 __global__ void __launch_bounds__(256) plain_kernel(KArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const Shared sh = setup_shared<R, FORM_PLAIN>(a, smem);
+    const Shared sh = setup_shared<R, FORM_PLAIN, false>(a, smem);
     const uint64_t q = a.qbegin + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q < a.total) {
         const int job = find_job(a.jobs, a.n_jobs, q, 0);
@@ -1565,7 +1552,7 @@ template <typename R, int G, bool BOUNDED, bool JL>
 __global__ void __launch_bounds__(1024) persistent_kernel(KArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const Shared sh = setup_shared<R, FORM_PERSISTENT>(a, smem);
+    const Shared sh = setup_shared<R, FORM_PERSISTENT, JL>(a, smem);
     constexpr int PF = BOUNDED ? FORM_EPOCH : FORM_PERSISTENT;
     const JobDev *const jt = JL ? sh.ljobs : a.jobs;
     const int lane = (int)(threadIdx.x & 63);
