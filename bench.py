@@ -140,7 +140,7 @@ def op_costs(b):
 # WRITE_SIZE runs (profiles/), scaled by the same counters' reading for a plain
 # device copy of known size (bench.py --copy-probe); valid only for the kernel
 # source it was measured on.
-TRAFFIC = {"kernel_sha1": "4d80a0076ffeceff45462c75a59d1795746b6454", "bytes": 54574141}  # profiles/persistent_kernel_slab_12films_counters.md
+TRAFFIC = {"kernel_sha1": "4adf109c3c2fedfd353c3657fb61159a4fa0fa08", "bytes": 54574142}  # profiles/persistent_kernel_slab_12films_counters.md
 CU, LANES_PER_CU_CLK, CLOCK = 256, 64, 2.4e9
 PEAK_LANE_OPS = CU * LANES_PER_CU_CLK * CLOCK  # 3.93e13 full-rate VALU lane-ops/s
 
