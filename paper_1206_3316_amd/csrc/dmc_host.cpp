@@ -449,16 +449,22 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
                        LaunchPlan &plan)
 {
     int spec = launch_spec(M, devs, n_jobs);
-    // the persistent half-space kernel (not time-bounded) reads the sample times
-    // from LDS: all of the launch's times must fit, else the generic kernel runs
     int32_t n_times_all = 0;
     for (int i = 0; i < n_jobs; ++i) n_times_all = std::max(n_times_all, devs[i].times_off + devs[i].n_times);
     const bool bounded_launch = b.drain_iters > 0 || b.n_resume > 0;
+    // LDS of a persistent workgroup: gain table + per-state data, the per-job
+    // counters, the sample times and the job table, then privatised tallies while
+    // they fit
+    const size_t tab = (((size_t)(1 << M->gain.bits) * 4 + 15) & ~size_t(15)) + (size_t)M->K * 16;
+    const size_t cap = (size_t)max_lds_bytes();
+    const size_t stats_lds = (n_jobs <= kLdsStatJobs) ? (size_t)n_jobs * kStats * 8 : 0;
     // persistent launches read the job table and the sample times from LDS when both
-    // fit; the specialised kernels exist only in that form, so larger tables take
-    // the generic kernel
+    // fit (beside the material's tables); the specialised kernels exist only in that
+    // form, so larger tables take the generic kernel
+    const size_t lds_tables = (size_t)n_times_all * 8 + 16 + (size_t)n_jobs * sizeof(JobDev);
     const bool jobs_lds = o.form == DMC_FORM_PERSISTENT &&
-                          (size_t)n_jobs * sizeof(JobDev) <= (size_t)kLdsJobsBytes && n_times_all <= kLdsTimes;
+                          (size_t)n_jobs * sizeof(JobDev) <= (size_t)kLdsJobsBytes && n_times_all <= kLdsTimes &&
+                          tab + stats_lds + lds_tables + 1024 <= cap;
     if (o.form == DMC_FORM_PERSISTENT && !jobs_lds) spec = GEOM_ANY;
     const bool times_lds = jobs_lds;
     KArgs a{};
@@ -492,7 +498,7 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
     a.nscat_out = o.nscat_out;
     a.stats = b.stats;
     a.kpad = 1 << M->gain.bits;
-    a.lds_stats = (n_jobs <= kLdsStatJobs) ? 1 : 0;
+    a.lds_stats = stats_lds > 0 ? 1 : 0;
     a.drain_iters = b.drain_iters;
     a.n_resume = b.n_resume;
     a.resume_in = b.resume_in;
@@ -509,7 +515,6 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
     if ((b.drain_iters || b.n_resume) && o.form != DMC_FORM_PERSISTENT)
         return fail(DMC_E_INVALID, "time-bounded launches need the persistent form");
     if (b.n_resume && !b.drain_iters) return fail(DMC_E_INVALID, "resuming needs a time-bounded launch");
-    const size_t stats_lds = a.lds_stats ? (size_t)n_jobs * kStats * 8 : 0;
     a.times_lds = times_lds ? n_times_all : 0;
     a.jobs_lds = jobs_lds ? 1 : 0;
     // sample times after the counters, then the job table at a 16-byte boundary
@@ -522,9 +527,6 @@ dmc_status plan_launch(const dmc_material *M, JobDev *devs, int n_jobs, const La
     int block = 256, grid = 1;
     size_t lds_bytes = 0;
     if (o.form == DMC_FORM_PERSISTENT) {
-        // LDS: gain table + per-state data, then privatised tallies while they fit
-        const size_t tab = (((size_t)a.kpad * 4 + 15) & ~size_t(15)) + (size_t)M->K * 16;
-        const size_t cap = (size_t)max_lds_bytes();
         if (tab + stats_lds + tail_bytes + 1024 > cap)
             return fail(DMC_E_UNSUPPORTED, "persistent form: material tables do not fit in LDS");
         const size_t budget = (cap - tab - stats_lds - tail_bytes - 16) / 8;  // doubles

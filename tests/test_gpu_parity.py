@@ -276,9 +276,10 @@ def test_batch_equals_solo_and_parameter_invariance():
 def test_launches_beyond_the_lds_tables_equal_solo_runs():
     """A launch whose job table exceeds its LDS copy (over 113 jobs) runs the
     generic kernel with the table in global memory, and a half-space launch whose
-    sample times exceed theirs (over 2048) the generic kernel too: each job's
-    tallies equal its solo run, which takes a specialised kernel with both tables
-    in LDS."""
+    sample times exceed theirs (over 2048) the generic kernel too, and so does a
+    launch whose tables fit on their own but not beside a large material's: each
+    job's tallies equal its solo run, which takes a specialised kernel with both
+    tables in LDS."""
     from gpu_cases import small_spot
     si = di.silicon_like()
     mat = b.Material(si)
@@ -300,6 +301,17 @@ def test_launches_beyond_the_lds_tables_equal_solo_runs():
     batch = b.simulate(spots, material=mat)
     for j in range(3):
         solo = b.simulate([spots[j]], material=mat)
+        assert rel_diff(batch.raw(j), solo.raw(0)) <= 1e-12, j
+    # a material of 5000 states (tables of 112 KiB): 100 jobs and 2000 sample times
+    # would fit in LDS on their own, but not beside its tables
+    print("case 5000-state material, 100 jobs, 2000 sample times", flush=True)
+    big = di.silicon_like(n_bins=2500)
+    bmat = b.Material(big)
+    jobs = [di.slab_job(big, 50e-9 + 2e-9 * i, 200, seed=7000 + i, n_bins=4) for i in range(98)]
+    jobs += [small_spot(n=300, seed=7100 + i, grid=4, n_times=1000, t_max=1e-10, mat=big) for i in range(2)]
+    batch = b.simulate(jobs, material=bmat)
+    for j in (0, 97, 98, 99):
+        solo = b.simulate([jobs[j]], material=bmat)
         assert rel_diff(batch.raw(j), solo.raw(0)) <= 1e-12, j
 
 
