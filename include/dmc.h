@@ -234,14 +234,26 @@ typedef struct dmc_result dmc_result;
 /* Bytes of device workspace a launch of these jobs needs (tallies, queue, counters). */
 dmc_status dmc_workspace_size(const dmc_job *jobs, int32_t n_jobs, const dmc_run_opts *opts, size_t *bytes);
 
-/* Runs one simulation; asynchronous on opts->stream.  Equivalent to a batch of one. */
+/* Runs one simulation; asynchronous on opts->stream.  Equivalent to a batch of
+ * one (same limits and errors as dmc_simulate_batch). */
 dmc_status dmc_simulate(const dmc_material *material, const dmc_geometry *geometry, const dmc_source *source,
                         uint64_t n_particles, uint64_t seed, const dmc_tally_desc *tally, const double *times,
                         int32_t n_times, const dmc_run_opts *opts, dmc_result **out);
 
 /* Runs n_jobs simulations in ONE launch (persistent form: one particle queue
  * over all jobs; plain form: one launch per job on the same stream).
- * Asynchronous on opts->stream. */
+ * Asynchronous on opts->stream.  jobs: 1..4096 descriptors, read during the
+ * call.  Per job: n_particles >= 1 (first_particle + n_particles must not
+ * wrap), n_bins 0..4096 (slab and film geometries only), n_batches 2..256,
+ * kmax >= -1, n_hj 0..min(kmax, 1024), n_times 0..1024 positive, strictly
+ * increasing times (transient sources only).  *out owns the tallies until
+ * dmc_result_destroy.
+ * Errors: DMC_E_INVALID (a limit above; a source, geometry and tally that do
+ * not go together; nscat_out_len too small), DMC_E_UNSUPPORTED (a valid
+ * request the kernels do not run: steady sources with snapshot times, or
+ * material tables larger than the LDS of the persistent form), DMC_E_NOMEM
+ * (allocation failed, or the caller's workspace is smaller than
+ * dmc_workspace_size), DMC_E_DEVICE. */
 dmc_status dmc_simulate_batch(const dmc_job *jobs, int32_t n_jobs, const dmc_run_opts *opts, dmc_result **out);
 
 /* ---- The batched launch for callers that cannot allocate ----

@@ -370,6 +370,51 @@ def small_spot_job():
     return small_spot(n=2000, seed=406, grid=8, n_times=4)
 
 
+def test_limits_hold_at_the_bound_and_fail_past_it():
+    """The limits of dmc_simulate_batch: each is accepted at its bound and refused
+    one past it with DMC_E_INVALID; at the largest bin count (tallies too large
+    for LDS, added in HBM) the FP64 kernel still matches the oracle."""
+    from gpu_cases import small_spot
+    si = di.silicon_like()
+    mat = b.Material(si)
+
+    def slab(**tally):
+        job = di.slab_job(si, 100e-9, 50, seed=11, n_bins=4)
+        for k, v in tally.items():
+            setattr(job.tally, k, v)
+        return job
+
+    def refused(jobs):
+        with pytest.raises(b.DmcError) as e:
+            b.simulate(jobs, material=mat)
+        assert e.value.code == b.DMC_E_INVALID
+
+    print("case past the bounds", flush=True)
+    empty = slab()
+    empty.n_particles = 0
+    refused([empty])
+    refused([slab(n_bins=4097)])
+    refused([slab(n_batches=1)])
+    refused([slab(n_batches=257)])
+    refused([di.pore_cell(60e-9, 0.2, 50, seed=12, material=si, kmax=1025, n_hj=1025)])
+    refused([small_spot(n=50, seed=13, grid=4, n_times=1025)])
+    refused([slab() for _ in range(4097)])
+    print("case at the bounds", flush=True)
+    res = b.simulate([slab() for _ in range(4096)], material=mat)
+    assert res.stats(4095).particles == 50
+    jobs = [di.pore_cell(60e-9, 0.2, 50, seed=12, material=si, kmax=1024, n_hj=1024),
+            small_spot(n=50, seed=13, grid=4, n_times=1024), slab(n_batches=2), slab(n_batches=256)]
+    res = b.simulate(jobs, material=mat)
+    assert [res.stats(j).particles for j in range(4)] == [50] * 4
+    print("case 4096 bins fp64 against the oracle", flush=True)
+    job = di.slab_job(si, 100e-9, 2000, seed=14, n_bins=4096)
+    prep = oracle.prepare(job)
+    oraw, _, _ = oracle.run_raw(job, threads=4, prep=prep)
+    res = b.simulate([job], material=mat, precision="fp64")
+    worst, ok = compare_sections(lib_sections(job, res.raw(0)), oracle.split_raw(prep, oraw), 1e-9, vmax_of(job))
+    assert ok, worst
+
+
 def test_invalid_jobs_are_rejected():
     si = di.silicon_like()
     # steady fields: pore cells only, grid (nx, 1, nz), bounds the unit cell
