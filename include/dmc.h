@@ -416,8 +416,10 @@ typedef struct dmc_server dmc_server;
 typedef struct {
     size_t memory_budget;  /* device bytes the admitted requests' tallies may hold */
     int32_t max_active;    /* requests resident at once (1..64) */
-    uint64_t epoch_flights; /* estimated flights per epoch launch, shared equally by the admitted
-                               requests (0 = 2e10) */
+    uint64_t epoch_flights; /* estimated flights per epoch launch (0 = 2e10): an epoch runs what
+                               equal shares of it would give the admitted requests (each at most
+                               its own remaining flights), handed out to the requests with the
+                               fewest flights left first */
     uint32_t drain_flights; /* flights a wave may still run once the epoch's queue is empty before
                                it suspends its live particles to the next epoch (0 = 2048) */
     int32_t class_epochs;  /* 0: every admitted request in every epoch, in the kernel that fits the

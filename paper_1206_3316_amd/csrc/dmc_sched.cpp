@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <iterator>
+#include <vector>
 
 namespace dmc {
 namespace sched {
@@ -118,6 +119,26 @@ uint64_t slice(double epoch_flights, size_t n_members, double flights_per_partic
     const double want = std::max(256.0, share / std::max(flights_per_particle, 1e-300));
     const uint64_t n = want >= 1.8e19 ? UINT64_MAX : (uint64_t)want;
     return std::min(n, left);
+}
+
+void slices(double epoch_flights, size_t n, const double *flights_per_particle, const uint64_t *left,
+            uint64_t *out)
+{
+    const double share = epoch_flights / (double)std::max<size_t>(n, 1);
+    std::vector<double> work(n);
+    std::vector<size_t> order(n);
+    double budget = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        work[i] = (double)left[i] * std::max(flights_per_particle[i], 0.0);
+        budget += std::min(work[i], share);
+        order[i] = i;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return work[a] < work[b]; });
+    for (size_t i : order) {
+        out[i] = budget > 0.0 ? slice(budget, 1, flights_per_particle[i], left[i]) : 0;
+        // a member that cannot take all it has left used up the budget
+        budget = out[i] < left[i] ? 0.0 : budget - (double)out[i] * flights_per_particle[i];
+    }
 }
 
 bool resume_map(const void *const *prev_members, const uint64_t *prev_suspended, size_t n_prev,

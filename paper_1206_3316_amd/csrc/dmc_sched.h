@@ -7,9 +7,9 @@
 // arrival order while a slot is free and their device tallies fit a first-fit
 // arena carved out of one allocation; each epoch takes the admitted requests of
 // one group (every request in group 0, or one class at a time, the classes in
-// turn), gives each member an equal share of the epoch's estimated flights, and
-// maps the particles its group suspended in its previous epoch back onto the
-// new epoch's job table.
+// turn), runs as many estimated flights as equal shares would, handed out to the
+// members nearest completion first, and maps the particles its group suspended in
+// its previous epoch back onto the new epoch's job table.
 #pragma once
 
 #include <cstddef>
@@ -56,6 +56,17 @@ int next_group(const bool *has, int n_classes, int next_class);
 // estimated flights over the members, divided by its flights per particle; at
 // least 256 and at most the particles it has left.
 uint64_t slice(double epoch_flights, size_t n_members, double flights_per_particle, uint64_t left);
+
+// Particles each of n members starts in an epoch (out[i]).  The epoch runs the
+// estimated flights that equal shares would, the sum over members of
+// min(remaining flights, epoch_flights / n) (remaining = left x flights per
+// particle), so it is as long as with equal shares; they go to the members in
+// order of remaining flights, smallest first (ties in member order), each taking
+// slice(budget left, 1, ...) until one cannot take all it has left, which spends
+// the budget; later members start none this epoch.  Requests nearest completion finish first, which shortens the
+// latency of most requests when sizes are heavy-tailed.
+void slices(double epoch_flights, size_t n, const double *flights_per_particle, const uint64_t *left,
+            uint64_t *out);
 
 // Resumed particles carry the slot (member index) of the epoch that suspended
 // them.  resume_job[i] receives the index in this epoch's members of previous

@@ -4,8 +4,9 @@
 // arena carved out of one allocation made at creation) are free.  Each epoch is
 // ONE persistent launch over a slice of every admitted request's particle
 // range, so a request that arrives while others run joins at the next epoch
-// and its particles share the device with theirs.  Slices are sized so each
-// admitted request receives an equal share of the epoch's estimated flights.
+// and its particles share the device with theirs.  An epoch runs the estimated
+// flights that equal shares would give its requests, handed out to the requests
+// with the fewest flights left first.
 // With class epochs, an epoch takes only the requests of one class (the classes
 // take turns), so it runs that class's specialised kernel.
 // Particles are independent and their random numbers are keyed by (seed, pid),
@@ -243,15 +244,21 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
         cls = sched::next_group(has, kClasses, S->next_class);
         if (cls < 0) return fail(DMC_E_DEVICE, "internal: no epoch group");
         S->next_class = (cls + 1) % kClasses;
-        size_t n_members = 0;
-        for (auto &rp : S->active) n_members += (rp->cls == cls) ? 1 : 0;
         const double epoch_flights = S->opts.epoch_flights ? (double)S->opts.epoch_flights : 2.0e10;
+        std::vector<double> fpp;
+        std::vector<uint64_t> left, given;
+        for (auto &rp : S->active) {
+            if (rp->cls != cls) continue;
+            fpp.push_back(rp->flights_per_particle);
+            left.push_back(rp->jh.dev.n - rp->cursor);
+        }
+        given.resize(left.size());
+        sched::slices(epoch_flights, left.size(), fpp.data(), left.data(), given.data());
         uint64_t base = 0;
         for (auto &rp : S->active) {
             Request *r = rp.get();
             if (r->cls != cls) continue;
-            const uint64_t left = r->jh.dev.n - r->cursor;
-            const uint64_t n = sched::slice(epoch_flights, n_members, r->flights_per_particle, left);
+            const uint64_t n = given[members.size()];
             JobDev d = r->jh.dev;
             const int64_t shift = (int64_t)(r->arena_off / sizeof(double));
             if (d.off_bins >= 0) d.off_bins += shift;

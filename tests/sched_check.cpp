@@ -2,6 +2,7 @@
 // dmc_sched.cpp), built with the address and undefined-behaviour sanitizers by
 // tests/test_host_sched.py.  Prints "ok" and exits 0 when every check holds.
 #include <cstdio>
+#include <algorithm>
 #include <cstdlib>
 #include <random>
 #include <vector>
@@ -101,6 +102,79 @@ static void slices()
     CHECK(slice(2e10, 3, 5.0, 0) == 0);
 }
 
+// Shortest-remaining-first slices: the epoch's budget is what equal shares would
+// run, and it goes to the members with the fewest flights left first.
+static void shortest_first_slices()
+{
+    {
+        // remaining flights 1e9, 3e10, 5e9, 0 (suspended particles only); share 5e9
+        const double fpp[4] = {100.0, 100.0, 50.0, 100.0};
+        const uint64_t left[4] = {10000000ull, 300000000ull, 100000000ull, 0ull};
+        uint64_t out[4];
+        slices(2e10, 4, fpp, left, out);
+        // budget = 1e9 + 5e9 + 5e9 + 0 = 1.1e10: member 3 (nothing left) takes none,
+        // member 0 all of its 1e9, member 2 all of its 5e9, member 1 the 5e9 left
+        CHECK(out[3] == 0 && out[0] == 10000000ull && out[2] == 100000000ull && out[1] == 50000000ull);
+        double run = 0.0, eq = 0.0;
+        for (int i = 0; i < 4; ++i) {
+            run += out[i] * fpp[i];
+            eq += (double)slice(2e10, 4, fpp[i], left[i]) * fpp[i];
+            CHECK(out[i] <= left[i]);
+        }
+        CHECK(run == 1.1e10 && eq == 1.1e10);  // as long as the equal-share epoch
+    }
+    {
+        // every member larger than its share: the smallest takes the whole budget
+        const double fpp[3] = {10.0, 10.0, 10.0};
+        const uint64_t left[3] = {9000000000ull, 3000000000ull, 6000000000ull};
+        uint64_t out[3];
+        slices(3e9, 3, fpp, left, out);
+        CHECK(out[1] == 300000000ull && out[0] == 0 && out[2] == 0);
+    }
+    {
+        // ties keep member order; the 256-particle floor holds while budget lasts
+        const double fpp[3] = {1e9, 1e9, 1e9};
+        const uint64_t left[3] = {1000, 1000, 1000};
+        uint64_t out[3];
+        slices(3e9, 3, fpp, left, out);  // share 1e9 = one particle each, budget 3e9
+        CHECK(out[0] == 256 && out[1] == 0 && out[2] == 0);
+    }
+    {
+        uint64_t out[1] = {7};
+        slices(2e10, 0, nullptr, nullptr, out);  // no members: nothing touched
+        CHECK(out[0] == 7);
+    }
+    // random members: never more than left, never negative budget overrun beyond
+    // one member's 256-particle floor, and the members served form a prefix of the
+    // order by remaining flights
+    std::mt19937_64 rng(777);
+    for (int trial = 0; trial < 500; ++trial) {
+        const size_t n = 1 + rng() % 32;
+        std::vector<double> fpp(n);
+        std::vector<uint64_t> left(n), out(n);
+        for (size_t i = 0; i < n; ++i) {
+            fpp[i] = 1.0 + (double)(rng() % 5000);
+            left[i] = (rng() % 4 == 0) ? 0 : rng() % 100000000ull;
+        }
+        const double E = 1e6 * (double)(1 + rng() % 100000);
+        slices(E, n, fpp.data(), left.data(), out.data());
+        double budget = 0.0, run = 0.0, fmax = 0.0;
+        for (size_t i = 0; i < n; ++i) {
+            budget += std::min((double)left[i] * fpp[i], E / (double)n);
+            run += (double)out[i] * fpp[i];
+            fmax = std::max(fmax, fpp[i]);
+            CHECK(out[i] <= left[i]);
+        }
+        CHECK(run <= budget + 256.0 * fmax);
+        for (size_t i = 0; i < n; ++i)
+            for (size_t j = 0; j < n; ++j) {
+                // a member with fewer flights left is served in full before one with more starts
+                const double wi = (double)left[i] * fpp[i], wj = (double)left[j] * fpp[j];
+                if (wi < wj && out[j] > 0) CHECK(out[i] == left[i]);
+            }
+    }
+}
+
 static void resume_mapping()
 {
     int r0, r1, r2, r3;
@@ -126,6 +200,7 @@ int main()
     admission_in_arrival_order();
     group_round_robin();
     slices();
+    shortest_first_slices();
     resume_mapping();
     if (failures) {
         std::fprintf(stderr, "%d checks failed\n", failures);
