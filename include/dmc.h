@@ -449,6 +449,13 @@ dmc_status dmc_server_submit(dmc_server *s, const dmc_job *job, uint64_t *ticket
 dmc_status dmc_server_step(dmc_server *s, int32_t *n_done);
 /* 1 if the ticket's request is complete, 0 if not (queued or running). */
 dmc_status dmc_server_poll(dmc_server *s, uint64_t ticket, int32_t *done);
+/* Runs epochs (dmc_server_step) until the ticket's request is complete (at
+ * once if it already is); the other admitted requests advance in the same
+ * epochs, and those that complete on the way stay ready for
+ * dmc_server_collect.  *n_epochs (may be NULL) receives the epochs run.
+ * Errors: DMC_E_INVALID (unknown or already collected ticket), those of
+ * dmc_server_step. */
+dmc_status dmc_server_wait(dmc_server *s, uint64_t ticket, int32_t *n_epochs);
 /* Takes a completed request's result (a one-job dmc_result owned by the caller). */
 dmc_status dmc_server_collect(dmc_server *s, uint64_t ticket, dmc_result **out);
 /* Requests queued / running. */

@@ -132,6 +132,7 @@ _SIGS = {
     "dmc_server_submit": ([C.c_void_p, C.POINTER(dmc_job), C.POINTER(C.c_uint64)], C.c_int32),
     "dmc_server_step": ([C.c_void_p, C.POINTER(C.c_int32)], C.c_int32),
     "dmc_server_poll": ([C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)], C.c_int32),
+    "dmc_server_wait": ([C.c_void_p, C.c_uint64, C.POINTER(C.c_int32)], C.c_int32),
     "dmc_server_collect": ([C.c_void_p, C.c_uint64, C.POINTER(C.c_void_p)], C.c_int32),
     "dmc_server_load": ([C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int32),
     "dmc_server_totals": ([C.c_void_p, C.POINTER(dmc_stats)], C.c_int32),
@@ -260,6 +261,10 @@ def dmc_server_step(server, n_done):
 
 def dmc_server_poll(server, ticket, done):
     return _call("dmc_server_poll", server, ticket, done)
+
+
+def dmc_server_wait(server, ticket, n_epochs):
+    return _call("dmc_server_wait", server, ticket, n_epochs)
 
 
 def dmc_server_collect(server, ticket, out):
@@ -718,6 +723,12 @@ class Server:
         d = C.c_int32()
         dmc_server_poll(self.handle, ticket, C.byref(d))
         return bool(d.value)
+
+    def wait(self, ticket: int) -> int:
+        """Runs epochs until the ticket's request is complete; returns the epochs run."""
+        n = C.c_int32()
+        dmc_server_wait(self.handle, ticket, C.byref(n))
+        return int(n.value)
 
     def collect(self, ticket: int) -> Result:
         h = C.c_void_p()

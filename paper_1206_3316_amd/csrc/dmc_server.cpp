@@ -366,6 +366,22 @@ extern "C" dmc_status dmc_server_poll(dmc_server *S, uint64_t ticket, int32_t *d
     return fail(DMC_E_INVALID, "unknown ticket");
 }
 
+extern "C" dmc_status dmc_server_wait(dmc_server *S, uint64_t ticket, int32_t *n_epochs)
+{
+    if (n_epochs) *n_epochs = 0;
+    for (;;) {
+        int32_t done = 0;
+        dmc_status st = dmc_server_poll(S, ticket, &done);
+        if (st != DMC_OK || done) return st;
+        // the request is queued or running: every epoch admits what fits (a
+        // request is only accepted if it fits alone) and starts particles of
+        // at least the admitted request with the fewest flights left, so with
+        // no new submissions every request ahead of this one, and it, complete
+        if ((st = dmc_server_step(S, nullptr)) != DMC_OK) return st;
+        if (n_epochs) ++*n_epochs;
+    }
+}
+
 extern "C" dmc_status dmc_server_collect(dmc_server *S, uint64_t ticket, dmc_result **out)
 {
     if (!S || !out) return fail(DMC_E_INVALID, "NULL argument");

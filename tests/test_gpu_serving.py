@@ -66,6 +66,32 @@ def test_mix_equals_alone_and_requests_join_running_epochs(class_epochs):
     srv.close()
 
 
+def test_wait_runs_epochs_until_the_request_completes():
+    """dmc_server_wait steps the server until one request is complete, the others
+    advancing with it; each result equals its solo run, and an unknown or
+    collected ticket is refused."""
+    si = di.silicon_like()
+    mat = b.Material(si)
+    reqs = _requests(si)[:3]
+    srv = b.Server(mat, memory_budget=64 << 20, max_active=3, epoch_flights=1e6)
+    tickets = [srv.submit(j) for j in reqs]
+    assert srv.wait(tickets[1]) >= 1
+    assert srv.done(tickets[1])
+    assert srv.wait(tickets[1]) == 0  # complete already: no epoch runs
+    for t in tickets:
+        srv.wait(t)
+    for t, job in zip(tickets, reqs):
+        res = srv.collect(t)
+        solo = b.simulate([job], material=mat)
+        assert rel_diff(res.raw(0), solo.raw(0)) <= 1e-12, job.name
+    for bad in (tickets[0], 10**9):
+        with pytest.raises(b.DmcError) as e:
+            srv.wait(bad)
+        assert e.value.code == b.DMC_E_INVALID
+    assert srv.load() == (0, 0)
+    srv.close()
+
+
 def test_request_larger_than_budget_is_rejected():
     si = di.silicon_like()
     mat = b.Material(si)
