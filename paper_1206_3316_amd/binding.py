@@ -480,6 +480,16 @@ class Result:
             pass
 
 
+def _workspace(workspace):
+    """(pointer, bytes) of a caller's device workspace, checked before any library
+    call: the library writes there from the device."""
+    if workspace is None:
+        return None, 0
+    if not getattr(workspace, "is_cuda", False) or not workspace.is_contiguous():
+        raise ValueError("workspace must be a contiguous CUDA tensor")
+    return workspace.data_ptr(), workspace.numel() * workspace.element_size()
+
+
 def _nscat_buffer(nscat_out, n_total: int):
     """(device pointer, entries) of a per-particle scattering-count tensor: a CUDA
     tensor of a 4-byte integer dtype with at least one entry per particle of the
@@ -505,6 +515,8 @@ def simulate(jobs, material: Optional[Material] = None, precision="fp32", form="
     """
     if not isinstance(jobs, (list, tuple)):
         jobs = [jobs]
+    ws_ptr, ws_bytes = _workspace(workspace)
+    ns_ptr, ns_len = _nscat_buffer(nscat_out, sum(int(j.n_particles) for j in jobs))
     material = material or Material(jobs[0].material)
     keep: list = [material]
     arr = (dmc_job * len(jobs))()
@@ -512,11 +524,8 @@ def simulate(jobs, material: Optional[Material] = None, precision="fp32", form="
         arr[i] = job_struct(j, material, keep)
     keep.append(arr)
     raw_stream = getattr(stream, "cuda_stream", stream)
-    ws_ptr, ws_bytes = None, 0
     if workspace is not None:
-        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
         keep.append(workspace)
-    ns_ptr, ns_len = _nscat_buffer(nscat_out, sum(int(j.n_particles) for j in jobs))
     if nscat_out is not None:
         keep.append(nscat_out)
     o = run_opts(precision, form, raw_stream, workspace=ws_ptr, workspace_bytes=ws_bytes, nscat_out=ns_ptr,
@@ -532,15 +541,14 @@ def simulate_one(job, material: Optional[Material] = None, precision="fp32", for
     point; whole particle range of the job's seed)."""
     if int(getattr(job, "first_particle", 0)) != 0:
         raise ValueError("dmc_simulate runs whole particle ranges; use simulate() for slices")
+    ws_ptr, ws_bytes = _workspace(workspace)
+    ns_ptr, ns_len = _nscat_buffer(nscat_out, int(job.n_particles))
     material = material or Material(job.material)
     keep: list = [material]
     j = job_struct(job, material, keep)
     raw_stream = getattr(stream, "cuda_stream", stream)
-    ws_ptr, ws_bytes = None, 0
     if workspace is not None:
-        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
         keep.append(workspace)
-    ns_ptr, ns_len = _nscat_buffer(nscat_out, int(job.n_particles))
     if nscat_out is not None:
         keep.append(nscat_out)
     o = run_opts(precision, form, raw_stream, workspace=ws_ptr, workspace_bytes=ws_bytes, nscat_out=ns_ptr,
@@ -577,7 +585,8 @@ def simulate_noalloc(jobs, raw_out, counters_out=None, material: Optional[Materi
             or not raw_out.is_contiguous():
         raise ValueError("raw_out must be a contiguous CUDA float64 tensor")
     if counters_out is not None and (not counters_out.is_cuda or counters_out.element_size() != 8
-                                     or counters_out.is_floating_point() or counters_out.numel() < 6 * len(jobs)):
+                                     or counters_out.is_floating_point() or not counters_out.is_contiguous()
+                                     or counters_out.numel() < 6 * len(jobs)):
         raise ValueError("counters_out must be a CUDA 64-bit integer tensor of 6 entries per job")
     keep: list = [material]
     arr = (dmc_job * len(jobs))()

@@ -144,3 +144,22 @@ def test_truncation_planning_validates_before_device_work():
 def test_debug_philox_rejects_null():
     rc = b.lib().dmc_debug_philox(1, None, None, None, None, 4)
     assert rc == b.DMC_E_INVALID
+
+
+def test_binding_refuses_host_buffers_for_device_outputs():
+    """A workspace or scattering-count buffer in host memory (or a strided one)
+    is refused by the binding before any library call: the kernels write to them
+    from the device."""
+    torch = pytest.importorskip("torch")
+    import dmc_inputs as di
+    job = di.gray_slab()
+    job.n_particles = 100
+    for kw in ({"workspace": torch.zeros(1 << 20, dtype=torch.uint8)},
+               {"nscat_out": torch.zeros(100, dtype=torch.int32)}):
+        with pytest.raises(ValueError):
+            b.simulate([job], **kw)
+        with pytest.raises(ValueError):
+            b.simulate_one(job, **kw)
+    strided = torch.zeros((100, 2), dtype=torch.int32)[:, 0]
+    with pytest.raises(ValueError):
+        b.simulate([job], nscat_out=strided)
