@@ -117,6 +117,11 @@ typedef struct {
     dmc_wall wall[2];
 } dmc_geometry_desc;
 
+/* Copies desc into an immutable handle (host memory only; no device work).
+ * Errors: DMC_E_INVALID (unknown kind or wall type; length not finite and > 0
+ * where used; pore radius outside [0, length/2); specularity outside [0, 1];
+ * an isothermal wall at T <= 0; periodic walls other than a plane pair; a pore
+ * or half-space surface that is not adiabatic), DMC_E_NOMEM. */
 dmc_status dmc_geometry_create(const dmc_geometry_desc *desc, dmc_geometry **out);
 dmc_status dmc_geometry_destroy(dmc_geometry *g);
 
