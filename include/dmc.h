@@ -438,10 +438,11 @@ typedef struct {
 } dmc_server_opts;
 
 /* The server admits requests while their device memory fits the budget and
- * a slot is free; each epoch is one persistent launch over a slice of the
- * particle range of every admitted request (of the epoch's class, see
- * class_epochs), so requests that arrive while others run join at a later
- * epoch.  Epochs are time-bounded: particles still in
+ * a slot is free; each epoch is one persistent launch over slices of the
+ * particle ranges of the admitted requests (of the epoch's class, see
+ * class_epochs), the epoch's flights going first to the requests with the
+ * fewest left (see epoch_flights), so requests that arrive while others run
+ * join at a later epoch.  Epochs are time-bounded: particles still in
  * flight when an epoch drains are suspended on the device and resumed first
  * in the next epoch with the same random-number counters, so results do not
  * depend on the slicing.  A request's tallies stay on the device until it
