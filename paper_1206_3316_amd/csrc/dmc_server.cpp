@@ -255,10 +255,15 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
         given.resize(left.size());
         sched::slices(epoch_flights, left.size(), fpp.data(), left.data(), given.data());
         uint64_t base = 0;
+        size_t k = 0;
         for (auto &rp : S->active) {
             Request *r = rp.get();
             if (r->cls != cls) continue;
-            const uint64_t n = given[members.size()];
+            const uint64_t n = given[k++];
+            // a request that starts no particle this epoch and has none suspended
+            // stays out of it, so that the epoch's kernel is chosen by the
+            // requests that run (one class: its specialised kernel)
+            if (n == 0 && r->suspended == 0) continue;
             JobDev d = r->jh.dev;
             const int64_t shift = (int64_t)(r->arena_off / sizeof(double));
             if (d.off_bins >= 0) d.off_bins += shift;
@@ -279,6 +284,10 @@ extern "C" dmc_status dmc_server_step(dmc_server *S, int32_t *n_done)
             devs.push_back(d);
             members.push_back(r);
         }
+        // the member with the fewest flights left starts particles if any has some
+        // left, and a member with none left has particles suspended (else it was
+        // complete and collected from the active set)
+        if (members.empty()) return fail(DMC_E_DEVICE, "internal: an epoch without work");
         // particles suspended last epoch resume first; their slots map to this
         // epoch's job table (jobs are queued in member order, so index = member)
         S->h_resume_job.assign((size_t)S->opts.max_active, 0);
