@@ -2,11 +2,12 @@
 //
 // Requests wait in a FIFO until a slot and enough device memory (a first-fit
 // arena carved out of one allocation made at creation) are free.  Each epoch is
-// ONE persistent launch over a slice of every admitted request's particle
-// range, so a request that arrives while others run joins at the next epoch
-// and its particles share the device with theirs.  An epoch runs the estimated
-// flights that equal shares would give its requests, handed out to the requests
-// with the fewest flights left first.
+// ONE persistent launch over slices of the admitted requests' particle ranges,
+// so a request that arrives while others run joins at a later epoch and its
+// particles share the device with theirs.  An epoch runs the estimated flights
+// that equal shares would give its requests, handed out to the requests with
+// the fewest flights left first; a request that starts nothing and has no
+// particle suspended sits the epoch out.
 // With class epochs, an epoch takes only the requests of one class (the classes
 // take turns), so it runs that class's specialised kernel.
 // Particles are independent and their random numbers are keyed by (seed, pid),
